@@ -1,0 +1,28 @@
+"""Build the FP64 CPU oracle (test infrastructure) into oracle/liboracle.so.
+
+Plain g++ with -O2, no contraction and no fast-math, so that every floating
+point operation is the correctly rounded binary64 operation the source names.
+"""
+import os
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "wcc_oracle.cpp")
+LIB = os.path.join(HERE, "liboracle.so")
+
+CXXFLAGS = ["-std=c++17", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
+            "-Wall", "-Wextra"]
+
+
+def build(verbose: bool = False) -> str:
+    cmd = ["g++", *CXXFLAGS, "-o", LIB + ".tmp", SRC]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    os.replace(LIB + ".tmp", LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    print(build(verbose="-v" in sys.argv))

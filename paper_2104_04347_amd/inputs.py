@@ -1,0 +1,243 @@
+"""Seeded synthetic initial data shared by the GPU path's tests, the benchmark
+and the CPU oracle's tests.
+
+This module holds problem data only -- initial conditions, their exact
+derivatives and exact cell integrals -- and none of the scheme's arithmetic.
+Every generator returns a state array of shape (nc, P+1, n) in float64 with
+
+* k = 0: the point value u0(x_j) at the cell centre, and
+* k >= 1: the scaled derivative dx^k u0^(k)(x_j) (Eq. 1D_Derivative_DEF),
+
+so that the cell polynomial of Eq. 1DPolynomial_Space is the degree-P Taylor
+polynomial of u0 at the centre.  A cell whose interior contains a jump of u0
+gets the exact mean of u0 over the cell (Gauss-Legendre on each smooth piece)
+as its value and zero derivatives.  The same bytes are fed to both
+implementations.
+
+Euler states are conserved variables (rho, rho u, rho e) with
+rho e = p/(gamma-1) + rho u^2/2 (Section 5.2 of the paper, perfect gas).
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+
+import numpy as np
+
+_GL_X, _GL_W = np.polynomial.legendre.leggauss(12)
+
+
+def centers(x_left: float, x_right: float, N: int, n_cells: int, parity: int) -> np.ndarray:
+    dx = (x_right - x_left) / N
+    return x_left + (np.arange(n_cells, dtype=np.float64) + 0.5 * (parity % 2)) * dx
+
+
+def n_cells(N: int, bc: str, parity: int) -> int:
+    if bc == "periodic":
+        return N
+    return N + 1 if parity % 2 == 0 else N
+
+
+# ---------------------------------------------------------------------------
+# Smooth scalar data: constant + sum of sines  c0 + sum_m A_m sin(w_m x + phi_m)
+# ---------------------------------------------------------------------------
+@dataclass
+class SineSum:
+    c0: float
+    amps: np.ndarray
+    freqs: np.ndarray   # angular wavenumbers w_m
+    phases: np.ndarray
+
+    def deriv(self, x: np.ndarray, k: int) -> np.ndarray:
+        """k-th derivative of u0 at x."""
+        out = np.full_like(x, self.c0 if k == 0 else 0.0, dtype=np.float64)
+        for a, w, ph in zip(self.amps, self.freqs, self.phases):
+            out = out + a * w ** k * np.sin(w * x + ph + k * np.pi / 2)
+        return out
+
+    def __call__(self, x):
+        return self.deriv(np.asarray(x, dtype=np.float64), 0)
+
+
+def taylor_scalar(fn: SineSum, x: np.ndarray, dx: float, P: int) -> np.ndarray:
+    q = np.empty((1, P + 1, x.size), dtype=np.float64)
+    for k in range(P + 1):
+        q[0, k] = dx ** k * fn.deriv(x, k)
+    return q
+
+
+def sine_wave(P: int, N: int, x_left: float, x_right: float, c0: float = 0.0, amp: float = 1.0,
+              w: float = np.pi, phase: float = 0.0, bc: str = "periodic", parity: int = 0):
+    """u0 = c0 + amp*sin(w x + phase) on the mesh of the given parity."""
+    fn = SineSum(c0, np.array([amp]), np.array([w]), np.array([phase]))
+    x = centers(x_left, x_right, N, n_cells(N, bc, parity), parity)
+    return taylor_scalar(fn, x, (x_right - x_left) / N, P), fn
+
+
+def burgers_modes(seed: int, P: int, N: int, x_left: float = 0.0, x_right: float = 2.0,
+                  n_modes: int = 3, c0: float = 0.5):
+    """u0 = c0 + sum of n_modes sines A_m sin(k_m pi x + phi_m), A_m ~ U(0, 0.5),
+    k_m uniform in {1,2,3,4}, phi_m ~ U(0, 2 pi), periodic on [0, 2]."""
+    rng = np.random.default_rng(seed)
+    amps = rng.uniform(0.0, 0.5, n_modes)
+    ks = rng.integers(1, 5, n_modes)
+    phases = rng.uniform(0.0, 2 * np.pi, n_modes)
+    fn = SineSum(c0, amps, ks * np.pi, phases)
+    x = centers(x_left, x_right, N, N, 0)
+    return taylor_scalar(fn, x, (x_right - x_left) / N, P), fn
+
+
+# ---------------------------------------------------------------------------
+# Piecewise Euler data: states (rho_s, u_s, p_s) with rho = rho_s*(1 + A sin(w x))
+# ---------------------------------------------------------------------------
+@dataclass
+class EulerPiecewise:
+    breaks: np.ndarray      # sorted jump positions inside the domain
+    rho: np.ndarray         # per piece (len(breaks)+1)
+    u: np.ndarray
+    p: np.ndarray
+    gamma: float = 1.4
+    sine_amp: float = 0.2
+    sine_w: float = 5.0
+    period: tuple | None = None   # (x_left, x_right) when the data wraps around
+    wrap_jump: bool = True        # periodic data: the state jumps at x_left == x_right
+
+    def piece(self, x: np.ndarray) -> np.ndarray:
+        return np.searchsorted(self.breaks, x, side="right")
+
+    def _wrap(self, x):
+        if self.period is None:
+            return x
+        a, b = self.period
+        return a + np.mod(x - a, b - a)
+
+    def conserved_deriv(self, x: np.ndarray, k: int) -> np.ndarray:
+        """k-th x-derivative of (rho, rho u, rho e) at x, shape (3, len(x))."""
+        xw = self._wrap(np.asarray(x, dtype=np.float64))
+        i = self.piece(xw)
+        rs, us, ps = self.rho[i], self.u[i], self.p[i]
+        w = self.sine_w
+        if k == 0:
+            rho = rs * (1.0 + self.sine_amp * np.sin(w * xw))
+            return np.stack([rho, rho * us, ps / (self.gamma - 1.0) + 0.5 * rho * us * us])
+        drho = rs * self.sine_amp * w ** k * np.sin(w * xw + k * np.pi / 2)
+        return np.stack([drho, drho * us, 0.5 * drho * us * us])
+
+    def cell_mean(self, xa: float, xb: float) -> np.ndarray:
+        """Exact mean of the conserved variables over [xa, xb] (Gauss-Legendre
+        on each smooth piece)."""
+        pts = [xa]
+        if self.period is None:
+            inner = [b for b in self.breaks if xa < b < xb]
+        else:
+            a, b0 = self.period
+            L = b0 - a
+            inner = []
+            cand = list(self.breaks) + ([a] if self.wrap_jump else [])
+            for sh in (-L, 0.0, L):
+                inner += [b + sh for b in cand if xa < b + sh < xb]
+            inner = sorted(inner)
+        pts += inner + [xb]
+        tot = np.zeros(3)
+        for lo, hi in zip(pts[:-1], pts[1:]):
+            if hi <= lo:
+                continue
+            mid, half = 0.5 * (lo + hi), 0.5 * (hi - lo)
+            xs = mid + half * _GL_X
+            # evaluate inside the piece: nudge the nodes away from the jump by construction
+            vals = self.conserved_deriv(xs, 0)
+            tot += half * (vals * _GL_W).sum(axis=1)
+        return tot / (xb - xa)
+
+    def jumps_in(self, xa: float, xb: float) -> bool:
+        if self.period is None:
+            return any(xa < b < xb for b in self.breaks)
+        a, b0 = self.period
+        L = b0 - a
+        cand = list(self.breaks) + ([a] if self.wrap_jump else [])
+        return any(xa < b + sh < xb for b in cand for sh in (-L, 0.0, L))
+
+
+def euler_taylor(data: EulerPiecewise, x: np.ndarray, dx: float, P: int) -> np.ndarray:
+    q = np.empty((3, P + 1, x.size), dtype=np.float64)
+    for k in range(P + 1):
+        q[:, k, :] = dx ** k * data.conserved_deriv(x, k)
+    for j, xc in enumerate(x):
+        xa, xb = xc - 0.5 * dx, xc + 0.5 * dx
+        if data.jumps_in(xa, xb):
+            q[:, 0, j] = data.cell_mean(xa, xb)
+            q[:, 1:, j] = 0.0
+    return q
+
+
+def draw_state(rng: np.random.Generator):
+    """(rho, u, p) with rho ~ U(0.1, 1), u ~ U(-1, 1), p ~ U(0.1, 1)."""
+    return rng.uniform(0.1, 1.0), rng.uniform(-1.0, 1.0), rng.uniform(0.1, 1.0)
+
+
+def euler_riemann(seed: int, P: int, N: int, x_left: float = 0.0, x_right: float = 1.0,
+                  x_jump: float = 0.5, gamma: float = 1.4, bc: str = "transmissive", parity: int = 0):
+    """Seeded left/right states with a jump at x_jump and the density sine
+    rho = rho_side*(1 + 0.2 sin 5x)."""
+    rng = np.random.default_rng(seed)
+    l, r = draw_state(rng), draw_state(rng)
+    data = EulerPiecewise(np.array([x_jump]), np.array([l[0], r[0]]), np.array([l[1], r[1]]),
+                          np.array([l[2], r[2]]), gamma=gamma,
+                          period=(x_left, x_right) if bc == "periodic" else None)
+    x = centers(x_left, x_right, N, n_cells(N, bc, parity), parity)
+    return euler_taylor(data, x, (x_right - x_left) / N, P), data
+
+
+def euler_multi_jump(seed: int, P: int, N: int, n_jumps: int = 8, x_left: float = 0.0,
+                     x_right: float = 1.0, gamma: float = 1.4, bc: str = "periodic", parity: int = 0):
+    """n_jumps sorted jump positions ~ U(0.05, 0.95), n_jumps+1 seeded states, density sine."""
+    rng = np.random.default_rng(seed)
+    breaks = np.sort(rng.uniform(0.05, 0.95, n_jumps))
+    st = np.array([draw_state(rng) for _ in range(n_jumps + 1)])
+    data = EulerPiecewise(x_left + (x_right - x_left) * breaks, st[:, 0], st[:, 1], st[:, 2], gamma=gamma,
+                          period=(x_left, x_right) if bc == "periodic" else None)
+    x = centers(x_left, x_right, N, n_cells(N, bc, parity), parity)
+    return euler_taylor(data, x, (x_right - x_left) / N, P), data
+
+
+def euler_uniform(N: int, P: int, rho: float, u: float, p: float, gamma: float = 1.4,
+                  bc: str = "periodic", parity: int = 0) -> np.ndarray:
+    n = n_cells(N, bc, parity)
+    q = np.zeros((3, P + 1, n), dtype=np.float64)
+    q[0, 0] = rho
+    q[1, 0] = rho * u
+    q[2, 0] = p / (gamma - 1.0) + 0.5 * rho * u * u
+    return q
+
+
+def euler_entropy_wave(P: int, N: int, x_left: float = 0.0, x_right: float = 2.0, amp: float = 0.2,
+                       u: float = 1.0, p: float = 1.0, gamma: float = 1.4):
+    """rho = 1 + amp sin(pi x), constant u and p, periodic on [0, 2]: the exact
+    solution is the shifted density profile."""
+    data = EulerPiecewise(np.array([]), np.array([1.0]), np.array([u]), np.array([p]), gamma=gamma,
+                          sine_amp=amp, sine_w=np.pi, period=(x_left, x_right), wrap_jump=False)
+    x = centers(x_left, x_right, N, N, 0)
+    return euler_taylor(data, x, (x_right - x_left) / N, P), data
+
+
+# ---------------------------------------------------------------------------
+# Batched workload: independent Euler instances of uneven size and degree.
+# ---------------------------------------------------------------------------
+@dataclass
+class BatchSpec:
+    N: np.ndarray      # mesh intervals per instance
+    P: np.ndarray      # degree per instance
+    seeds: np.ndarray  # per-instance data seeds
+
+
+def batch_spec(B: int, seed: int, n_lo: int = 256, n_hi: int = 65536, degrees=(1, 2, 3)) -> BatchSpec:
+    """N_b = round(exp(U(ln n_lo, ln n_hi))), P_b uniform over degrees."""
+    rng = np.random.default_rng(seed)
+    N = np.rint(np.exp(rng.uniform(np.log(n_lo), np.log(n_hi), B))).astype(np.int64)
+    P = rng.choice(np.asarray(degrees), B).astype(np.int32)
+    seeds = rng.integers(0, 2 ** 31 - 1, B)
+    return BatchSpec(N, P, seeds)
+
+
+def batch_instance(spec: BatchSpec, b: int, gamma: float = 1.4):
+    """Riemann problem with density sine on [0, 1], transmissive, for instance b."""
+    return euler_riemann(int(spec.seeds[b]), int(spec.P[b]), int(spec.N[b]), gamma=gamma)[0]

@@ -1,0 +1,148 @@
+"""Pins of the oracle against exact solutions of the PDEs: the design order
+P+1 of the scheme (abstract; Section 5.1) and shock capturing.
+
+* Advection u0 = 1 + 0.2 sin(pi x) on [0, 2] (exact shift), P = 2, N = 50..800.
+* Euler entropy wave rho = 1 + 0.2 sin(pi x), u = p = 1 (exact shift).
+* Euler, gamma = 3, isentropic: exact smooth solution by characteristics.
+* Burgers before the shock: method of characteristics.
+* Burgers after the shock: Hopf-Lax formula, first-order L1 convergence.
+* Sod's shock tube (Section 5.2): exact Riemann solution.
+"""
+import numpy as np
+import pytest
+import sympy as sp
+
+import exact
+import oracle
+from paper_2104_04347_amd import inputs
+
+
+def orders(errs):
+    e = np.asarray(errs)
+    return np.log2(e[:-1] / e[1:])
+
+
+def test_advection_c1_third_order():
+    """u_t + u_x = 0, u0 = 1 + 0.2 sin(pi x) on [0, 2], P = 2, t = 2, CFL 0.25
+    per half-step: design order 3 over N = 50..800."""
+    errs = []
+    for N in (50, 100, 200, 400, 800):
+        pb = oracle.Problem("advection", 2, N, x_left=0.0, x_right=2.0, a=1.0)
+        q, fn = inputs.sine_wave(2, N, 0.0, 2.0, c0=1.0, amp=0.2)
+        r = oracle.run(pb, q, t_end=2.0, cfl=0.25)
+        x = pb.centers(r.parity)
+        errs.append(np.abs(r.q[0, 0] - fn(x - r.t)).mean())
+    o = orders(errs)
+    assert np.all(np.abs(o - 3.0) < 0.1), o
+
+
+@pytest.mark.parametrize("P,lim", [(1, False), (2, False), (3, False), (4, False)])
+def test_euler_entropy_wave_order(P, lim):
+    """Entropy wave, limiter off (see the Burgers test below for why the limiter
+    is excluded from the order pins)."""
+    errs = []
+    Ns = (20, 40, 80, 160) if P >= 3 else (40, 80, 160, 320)
+    nu = {1: 0.4, 2: 0.3, 3: 0.25, 4: 0.25}[P]
+    for N in Ns:
+        pb = oracle.Problem("euler", P, N, x_left=0.0, x_right=2.0, limiter=lim)
+        q, data = inputs.euler_entropy_wave(P, N)
+        r = oracle.run(pb, q, t_end=0.5, cfl=nu)
+        assert r.flags == 0
+        x = pb.centers(r.parity)
+        want = data.conserved_deriv(x - r.t, 0)
+        errs.append(np.abs(r.q[0, 0] - want[0]).mean())
+    o = orders(errs)
+    assert np.all(o > P + 1 - 0.2), o
+
+
+@pytest.mark.parametrize("P", [1, 2, 3, 4])
+def test_euler_gamma3_simple_wave_order(P):
+    """Nonlinear smooth Euler flow (gamma = 3) before any shock forms: order P+1
+    in all three conserved variables.  Exercises the Taylor quotient and
+    products of the system CK."""
+    x = sp.Symbol("x", real=True)
+    flow = exact.Gamma3Flow(0.1 * sp.sin(sp.pi * x + 1), 1 + 0.1 * sp.sin(sp.pi * x))
+    t_end = 0.4
+    errs = []
+    Ns = (40, 80, 160, 320)
+    for N in Ns:
+        pb = oracle.Problem("euler", P, N, x_left=0.0, x_right=2.0, gamma=3.0)
+        xc = pb.centers(0)
+        q = flow.taylor_state(xc, pb.dx, P)
+        r = oracle.run(pb, q, t_end=t_end, cfl=0.2)
+        assert r.flags == 0
+        xe = pb.centers(r.parity)
+        want = flow.exact_conserved(xe, r.t)
+        errs.append(np.abs(r.q[:, 0] - want).mean())
+    o = orders(errs)
+    assert np.all(o > P + 1 - 0.25), o
+
+
+@pytest.mark.parametrize("P,lim", [(1, False), (2, False), (3, False), (4, False)])
+def test_burgers_before_shock_order(P, lim):
+    """C2-type data (seeded sum of three sines around 0.5 on [0, 2]) up to half
+    the breaking time, against the method of characteristics.  Limiter off: the
+    paper's order argument for the limiter (Eq. 1DWmError) assumes beta_m of
+    the linear candidates scales like dx^2; where a candidate's slope passes
+    through zero the weights are not small and the limiter does act on this
+    data (recorded in the design notes)."""
+    q0, fn = inputs.burgers_modes(0, P, 10)
+    tb = exact.breaking_time(fn)
+    t_end = 0.5 * tb
+    nu = {1: 0.4, 2: 0.3, 3: 0.25, 4: 0.25}[P]
+    errs = []
+    Ns = (200, 400, 800, 1600) if P <= 2 else (100, 200, 400, 800)
+    for N in Ns:
+        pb = oracle.Problem("burgers", P, N, x_left=0.0, x_right=2.0, limiter=lim)
+        q, _ = inputs.burgers_modes(0, P, N)
+        r = oracle.run(pb, q, t_end=t_end, cfl=nu)
+        assert r.flags == 0
+        x = pb.centers(r.parity)
+        errs.append(np.abs(r.q[0, 0] - exact.burgers_moc(fn, x, r.t)).mean())
+    o = orders(errs)
+    assert np.all(o[1:] > P + 1 - 0.2), (errs, o)
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("P", [1, 2, 3])
+def test_burgers_after_shock_hopf_lax(P):
+    """Past the shock (3 t_b) the limited scheme converges to the entropy
+    solution given by the Hopf-Lax formula, at about first order in L1."""
+    _, fn = inputs.burgers_modes(0, P, 10)
+    tb = exact.breaking_time(fn)
+    t_end = 3.0 * tb
+    nu = {1: 0.4, 2: 0.3, 3: 0.25}[P]
+    errs = []
+    for N in (200, 400, 800, 1600):
+        pb = oracle.Problem("burgers", P, N, x_left=0.0, x_right=2.0, limiter=True)
+        q, _ = inputs.burgers_modes(0, P, N)
+        r = oracle.run(pb, q, t_end=t_end, cfl=nu)
+        assert r.flags == 0
+        x = pb.centers(r.parity)
+        errs.append(np.abs(r.q[0, 0] - exact.burgers_hopf_lax(fn, x, r.t, n_grid=801)).mean())
+    # The error sits in the one or two cells the shock is spread over, so the
+    # per-level order is noisy; over a factor 8 in N it must average > 0.67.
+    assert errs[-1] < 2e-4 and errs[0] / errs[-1] > 4.0, errs
+
+
+@pytest.mark.parametrize("P", [1, 2, 3])
+def test_sod_shock_tube(P):
+    """Section 5.2: Sod on [0, 2], jump at x = 1, t = 0.4, transmissive ends.
+    L1 density error against the exact Riemann solution shrinks with the mesh;
+    no new extrema beyond 5% of the jump (oscillation control by the limiter)."""
+    WL, WR = (1.0, 0.0, 1.0), (0.125, 0.0, 0.1)
+    errs = []
+    for N in (100, 200, 400):
+        pb = oracle.Problem("euler", P, N, bc="transmissive", x_left=0.0, x_right=2.0, limiter=True)
+        data = inputs.EulerPiecewise(np.array([1.0]), np.array([1.0, 0.125]), np.array([0.0, 0.0]),
+                                     np.array([1.0, 0.1]), sine_amp=0.0)
+        q = inputs.euler_taylor(data, pb.centers(0), pb.dx, P)
+        r = oracle.run(pb, q, t_end=0.4, cfl={1: 0.4, 2: 0.3, 3: 0.25}[P])
+        assert r.flags == 0
+        x = pb.centers(r.parity)
+        ex = exact.riemann_sample(WL, WR, (x - 1.0) / r.t)
+        rho = r.q[0, 0]
+        errs.append(np.abs(rho - ex[0]).mean())
+        assert rho.max() <= 1.0 + 0.05 * 0.875 and rho.min() >= 0.125 - 0.05 * 0.875
+    assert errs[0] > errs[1] > errs[2], errs
+    assert errs[-1] < 6e-3, errs
