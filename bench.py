@@ -1,0 +1,257 @@
+#!/usr/bin/env python3
+"""Benchmark of the WCC half-step on one MI355X.
+
+Workload (the headline configuration): 1D Euler, gamma = 1.4, on [0, 1] with
+N = 1,048,576 mesh intervals, degree P = 3 (4th order), seeded Riemann data
+(rho ~ U(0.1, 1), u ~ U(-1, 1), p ~ U(0.1, 1) on each side of x = 0.5) with the
+density sine rho*(1 + 0.2 sin 5x), transmissive ends, limiter on (characteristic
+variables), CFL 0.25 per half-step.  A step is one half-step of the whole path
+(expansion, flux integral, average and derivative update, limiter, wave speed,
+time control) over all cells; inputs are resident in HBM before timing starts.
+
+Printed: one JSON line.  `value` is cell-DOF updates per second in binary64
+(the bit-exact mode); the FP32-mixed mode, the batched workload (4096 uneven
+instances, solves/s for 100 half-steps each) and the oracle's CPU timing are
+reported beside it, with the roofline of the dominant kernel measured live with
+HIP events on the stream the kernels run on.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK = 8.0e12          # bytes/s, MI355X HBM3E
+FP64_VALU_PEAK = 78.6e12   # flop/s, fma counted as 2
+FP32_VALU_PEAK = 157.3e12  # flop/s (packed / dual-issue)
+CFL_BY_P = [0.4, 0.4, 0.3, 0.25, 0.25]
+
+
+def flop_counts():
+    with open(os.path.join(ROOT, "paper_2104_04347_amd", "flop_counts.json")) as f:
+        return json.load(f)["counts"]
+
+
+def cells_updated(N: int, bc: str, parity0: int, steps: int) -> int:
+    """New cells written over `steps` half-steps starting on mesh parity0."""
+    if bc == "periodic":
+        return N * steps
+    tot, par = 0, parity0
+    for _ in range(steps):
+        tot += N if par == 0 else N + 1   # original (N+1 cells) -> staggered (N) and back
+        par ^= 1
+    return tot
+
+
+def bytes_per_launch(N: int, P: int, nc: int, precision: str) -> float:
+    """Algorithmic HBM bytes of one half-step: every old cell read once and
+    every new cell written once (point value in binary64, derivatives in the
+    bulk type).  Averaged over the two parities of a transmissive run."""
+    b_cell = nc * (8 + P * (8 if precision == "fp64" else 4))
+    n_old_plus_new = 2 * N + 1
+    return float(n_old_plus_new * b_cell)
+
+
+def time_single(args, precision: str, q0):
+    import torch
+    from paper_2104_04347_amd import binding
+    P, N = args.P, args.N
+    s = binding.Solver("euler", P, N, "transmissive", limiter=True, precision=precision)
+    s.write(q0)
+    s.run(args.warmup, args.cfl)
+    torch.cuda.synchronize()
+    parity0 = s.info().parity
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record(stream)
+    s.run(args.steps, args.cfl)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ev_ms = e0.elapsed_time(e1)
+    lib_ms = s.last_run_ms()
+    info = s.info()
+    ok = (info.flags & 3) == 0
+    cells = cells_updated(N, "transmissive", parity0, args.steps)
+    dofs = cells * 3 * (P + 1)
+    out = dict(value=dofs / wall, wall_s=wall, event_ms=ev_ms, lib_event_ms=lib_ms, flags=int(info.flags),
+               ok=ok, t=info.t, half_steps=int(info.half_steps))
+    s.close()
+    return out
+
+
+def time_batch(args):
+    import torch
+    from paper_2104_04347_amd import binding, inputs
+    spec = inputs.batch_spec(args.batch_B, args.seed)
+    bt = binding.Batch("euler", spec.P, spec.N, "transmissive", limiter=True, precision="fp32_mixed")
+    sched = None
+    if args.batch_schedule:
+        sched = [int(v) for v in args.batch_schedule.split(",")]
+        bt.set_schedule(*sched)
+    for b in range(spec.P.size):
+        bt.write(b, inputs.batch_instance(spec, b))
+    bt.prepare()
+    bt.run(args.batch_warmup, CFL_BY_P)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    bt.run(args.batch_steps, CFL_BY_P)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = bt.last_run_ms()
+    flags = 0
+    for b in range(0, spec.P.size, max(1, spec.P.size // 64)):
+        flags |= bt.read(b)[1].flags & 3
+    cells = int(np.sum(spec.N)) * args.batch_steps          # ~N per half-step per instance
+    dofs = int(np.sum(spec.N * 3 * (spec.P + 1))) * args.batch_steps
+    bt.close()
+    return dict(value=spec.P.size / wall, unit="solves/s", instances=int(spec.P.size),
+                half_steps_each=args.batch_steps, wall_s=wall, event_ms=ms, cell_dof_per_s=dofs / wall,
+                total_cells=int(np.sum(spec.N)), cells_per_s=cells / wall, flags=int(flags),
+                schedule=sched or "default")
+
+
+def cpu_baseline(args, q0):
+    """The FP64 oracle as it stands, single-threaded, on a bounded sample of
+    the same workload: the first `cpu_steps` half-steps of the full mesh."""
+    import oracle
+    pb = oracle.Problem("euler", args.P, args.N, bc="transmissive", limiter=True)
+    t0 = time.perf_counter()
+    r = oracle.run(pb, q0, cfl=args.cfl, max_half_steps=args.cpu_steps)
+    wall = time.perf_counter() - t0
+    cells = cells_updated(args.N, "transmissive", 0, r.half_steps)
+    dofs = cells * 3 * (args.P + 1)
+    cpu_model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                cpu_model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"value": dofs / wall, "unit": "cell-DOF updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {r.half_steps} half-steps of the full workload (N={args.N}, P={args.P}), "
+                      f"FP64 oracle, single thread, {wall:.1f} s",
+            "cpu_model": cpu_model, "host_threads": os.cpu_count()}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000, help="timed half-steps")
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--P", type=int, default=3)
+    ap.add_argument("--N", type=int, default=1 << 20)
+    ap.add_argument("--cfl", type=float, default=0.25)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--batch-B", type=int, default=4096)
+    ap.add_argument("--batch-steps", type=int, default=100)
+    ap.add_argument("--batch-warmup", type=int, default=24)
+    ap.add_argument("--batch-schedule", default="", help="threads,blocks,mode for the batched kernels")
+    ap.add_argument("--cpu-steps", type=int, default=8)
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(a 1D slab decomposition is described in DESIGN.md); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2104_04347_amd import binding, inputs
+    if not torch.cuda.is_available():
+        print("bench.py needs the GPU", file=sys.stderr)
+        sys.exit(1)
+    binding.load()
+    torch.cuda.set_device(0)
+
+    q0, _ = inputs.euler_riemann(args.seed, args.P, args.N)
+    print(f"[bench] workload ready: Euler P={args.P} N={args.N}", file=sys.stderr, flush=True)
+    r64 = time_single(args, "fp64", q0)
+    print(f"[bench] fp64: {r64['value']:.3e} DOF/s", file=sys.stderr, flush=True)
+    rmx = None
+    if not args.no_mixed:
+        rmx = time_single(args, "fp32_mixed", q0)
+        print(f"[bench] fp32_mixed: {rmx['value']:.3e} DOF/s", file=sys.stderr, flush=True)
+    rb = None
+    if not args.no_batch:
+        rb = time_batch(args)
+        print(f"[bench] batched: {rb['value']:.1f} solves/s", file=sys.stderr, flush=True)
+
+    counts = flop_counts()
+    fl = counts[f"euler/P{args.P}/lim"]["flops"]
+
+    def roof(r, precision):
+        launch_s = (r["lib_event_ms"] / 1e3) / args.steps
+        bpl = bytes_per_launch(args.N, args.P, 3, precision)
+        cells_per_launch = args.N + 0.5
+        bw = bpl / launch_s
+        flops = fl * cells_per_launch / launch_s
+        peak_alu = FP64_VALU_PEAK if precision == "fp64" else FP32_VALU_PEAK
+        return dict(launch_us=launch_s * 1e6, bytes_per_launch=bpl, gbs=bw / 1e9, hbm_frac=bw / HBM_PEAK,
+                    tflops=flops / 1e12, alu_frac=flops / peak_alu, alu_peak=peak_alu)
+
+    ro = roof(r64, "fp64")
+    bound_hbm = ro["hbm_frac"] >= ro["alu_frac"]
+    roofline = {
+        "bound": "hbm" if bound_hbm else "alu",
+        "achieved": round(ro["gbs"], 1) if bound_hbm else round(ro["tflops"], 3),
+        "peak": HBM_PEAK / 1e9 if bound_hbm else FP64_VALU_PEAK / 1e12,
+        "unit": "GB/s" if bound_hbm else "TFLOP/s",
+        "frac": round(ro["hbm_frac"] if bound_hbm else ro["alu_frac"], 4),
+        "traffic": None,
+        "kernel": f"k_half_step<euler,P={args.P},limiter,f64>",
+        "launch_us": round(ro["launch_us"], 2),
+        "bytes_per_launch": ro["bytes_per_launch"],
+        "other_roof": ({"bound": "alu", "achieved": round(ro["tflops"], 3), "unit": "TFLOP/s",
+                        "peak": FP64_VALU_PEAK / 1e12, "frac": round(ro["alu_frac"], 4)} if bound_hbm else
+                       {"bound": "hbm", "achieved": round(ro["gbs"], 1), "unit": "GB/s",
+                        "peak": HBM_PEAK / 1e9, "frac": round(ro["hbm_frac"], 4)}),
+    }
+
+    line = {
+        "metric": "cell-DOF updates/s, 1D Euler P=3 (FP64 vs FP32-mixed); batched solves/s",
+        "value": r64["value"],
+        "unit": "cell-DOF updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": r64["wall_s"] * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"1D Euler gamma=1.4, N={args.N}, P={args.P}, seeded Riemann (seed {args.seed}) "
+                               f"+ density sine, transmissive, limiter on, CFL {args.cfl} per half-step",
+                   "N": args.N, "P": args.P, "precision": "fp64", "parallelism": "single GPU"},
+        "valid": bool(r64["ok"]),
+        "roofline": roofline,
+    }
+    if rmx is not None:
+        rm = roof(rmx, "fp32_mixed")
+        line["fp32_mixed"] = {"value": rmx["value"], "unit": "cell-DOF updates/s", "dtype": "f32 bulk + f64 average",
+                              "ms_per_step": rmx["wall_s"] * 1e3 / args.steps, "valid": bool(rmx["ok"]),
+                              "launch_us": round(rm["launch_us"], 2), "hbm_frac": round(rm["hbm_frac"], 4),
+                              "gbs": round(rm["gbs"], 1), "tflops": round(rm["tflops"], 3)}
+    if rb is not None:
+        line["batched"] = rb
+    if not args.no_cpu:
+        print("[bench] CPU baseline (oracle) ...", file=sys.stderr, flush=True)
+        line["cpu_baseline"] = cpu_baseline(args, q0)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,197 @@
+/* wcc.h -- C ABI of the MI355X (gfx950) library for the explicit half-step of
+ * the 1D weighted compact central (WCC) schemes of Shen & Parsani,
+ * "A class of high-order weighted compact central schemes for solving
+ * hyperbolic conservation laws" (arXiv:2104.04347).
+ *
+ * The library advances u_t + f(u)_x = 0 on [x_left, x_right] with initial
+ * data u0 and boundary values (problem statement, Eq. 1DHCL; for systems
+ * Eq. 1DHCLSystem) on the two space-time staggered meshes of Section 2.1.
+ * One half-step (t^n -> t^{n+1/2}) is one fused GPU kernel that runs the
+ * Cauchy-Kovalewski expansion (Eq. 1DCauchy_Kovalewski), the Riemann-solver
+ * free finite-volume update of the cell average (Eq. SubEq:1DIntegral with
+ * Eq. Cal1DFlux, SubEq:1DCellAVGR, SubEq:1DCellAVGL), the central-difference
+ * update of the derivatives (Eq. SubEq:Cal_1D_Derivatives_3 with
+ * SubEq:Cal_1D_Derivatives_4) and the WENO-type limiter (Section 2.2; for
+ * the Euler equations in characteristic variables, Section 4).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * - Every call returns int: WCC_OK (0) or a negative WCC_E* code.  Nothing
+ *   throws across the ABI.  wcc_strerror names a code; wcc_last_error gives
+ *   the last detailed message of a context.
+ * - State layout at the boundary: a host array of doubles indexed
+ *   [c][k][j] = host[(c*(P+1) + k)*n_cells + j] with c the component
+ *   (1 for scalars; rho, rho*u, rho*e for Euler), k = 0 the point value u at
+ *   the cell centre and k >= 1 the scaled derivative
+ *   u_kx = dx^k d^k u/dx^k at the centre (Eq. 1D_Derivative_DEF,
+ *   Eq. 1DPolynomial_Space; the vector q of Eq. 1DSchemeMatrixForm).
+ * - Meshes (Section 2.1): dx = (x_right-x_left)/N.  Parity 0 is the original
+ *   mesh, parity 1 the staggered one.  Periodic: N cells on both, centres
+ *   x_left + (j + parity/2) dx.  Otherwise the original mesh has the N+1
+ *   cells centred at x_left + j dx (j = 0..N) and the staggered mesh the N
+ *   cells centred at x_left + (j+1/2) dx.
+ * - Time step: the CFL number cfl is nu = max wave speed * dt / dx with dt the
+ *   HALF-step (t^{n+1/2} - t^n).  dt = (cfl*dx)/s_max with s_max the largest
+ *   wave speed (|a|, |u| or |u|+c) over the cell averages of the current state,
+ *   computed on the device; the step that would pass t_end is clipped to it.
+ * - Precision: WCC_FP64 computes everything in binary64 with a fixed,
+ *   documented operation order (no contraction); WCC_FP32_MIXED keeps the
+ *   point value / cell-average arithmetic in binary64 and runs the expansion,
+ *   the derivatives and the limiter in binary32 (derivatives stored as
+ *   float; the boundary still speaks doubles and rounds on write).
+ * - Ownership: device memory and the HIP stream belong to the caller and are
+ *   handed over with wcc_bind / wcc_batch_bind; the library never frees them.
+ *   Host buffers stay the caller's; reads and writes copy synchronously on
+ *   the bound stream.  wcc_destroy frees host-side state, graphs and the
+ *   library's own capture stream.  A context is not thread-safe; separate
+ *   contexts are independent.
+ * - Stream order: wcc_step and wcc_run only enqueue work; wcc_advance,
+ *   wcc_read_dofs, wcc_write_dofs and wcc_totals synchronise the bound
+ *   stream.
+ */
+#ifndef WCC_H
+#define WCC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define WCC_OK 0
+#define WCC_EINVAL (-1)      /* bad argument: P outside [0, WCC_PMAX], N < 2, bad enum, cfl outside (0, 1], t_end < t, ... */
+#define WCC_ESTATE (-2)      /* call out of order: not bound, or no state written yet */
+#define WCC_ESIZE (-3)       /* a buffer is smaller than required */
+#define WCC_EDEVICE (-4)     /* a HIP runtime call failed; wcc_last_error has its message */
+#define WCC_ENONFINITE (-5)  /* a non-finite value or rho <= 0 / p <= 0 appeared; the state is kept for
+                                inspection and further steps do nothing until the next write */
+
+#define WCC_PMAX 4
+
+enum { WCC_ADVECTION = 0, WCC_BURGERS = 1, WCC_EULER = 2 };        /* f = a u ; u^2/2 ; 1D Euler (Section 5.2) */
+enum { WCC_BC_PERIODIC = 0, WCC_BC_TRANSMISSIVE = 1, WCC_BC_DIRICHLET = 2 };
+enum { WCC_FP64 = 0, WCC_FP32_MIXED = 1 };
+
+typedef struct wcc_ctx wcc_ctx;       /* opaque, host side */
+typedef struct wcc_batch wcc_batch;   /* opaque, host side */
+
+typedef struct {
+  double x_left, x_right;        /* domain; default [0, 1] */
+  double a;                      /* advection speed (default 1) */
+  double gamma;                  /* ratio of specific heats (default 1.4, Section 5.2) */
+  double eps;                    /* limiter epsilon (default 1e-40, Eq. 1D2ndOrderWeights) */
+  int32_t limiter;               /* 1: apply the limiter (P >= 1), 0: linear scheme */
+  int32_t precision;             /* WCC_FP64 or WCC_FP32_MIXED */
+  double left_state[3];          /* Dirichlet ghost states, conserved variables */
+  double right_state[3];
+} wcc_params;
+
+typedef struct {
+  double t;                      /* current time */
+  int32_t parity;                /* mesh of the current state (0 original, 1 staggered) */
+  int32_t flags;                 /* bit 0: non-finite value, bit 1: rho <= 0 or p <= 0, bit 2: cfl above the linear limit */
+  int64_t n_cells;               /* cells on the current mesh */
+  double x_first_center;         /* centre of cell 0 */
+  double dx;
+  int64_t half_steps;            /* half-steps taken since the last wcc_write_dofs */
+  double s_max;                  /* largest wave speed of the current state */
+} wcc_state_info;
+
+/* Fill *p with the defaults listed above.  Returns WCC_EINVAL for p == NULL. */
+int wcc_params_default(wcc_params* p);
+
+/* Create a context for `equation` (WCC_ADVECTION/BURGERS/EULER), degree P in
+ * [0, WCC_PMAX] (scheme order P+1), N >= 2 mesh intervals and boundary
+ * condition bc.  params may be NULL (defaults).  On success *out owns a new
+ * context (free with wcc_destroy).  Errors: WCC_EINVAL. */
+int wcc_create(int equation, int P, int64_t N, int bc, const wcc_params* params, wcc_ctx** out);
+
+/* Device bytes the caller must provide to wcc_bind: ping-pong state buffers
+ * (structure of arrays, rows padded to 64 cells) and a small control block. */
+int wcc_workspace_bytes(const wcc_ctx* ctx, size_t* bytes);
+
+/* Hand over device memory (dev_ptr, at least wcc_workspace_bytes bytes,
+ * 256-byte aligned) and the HIP stream (hipStream_t as void*, NULL = the
+ * default stream) on which all work of this context is enqueued.
+ * Errors: WCC_EINVAL (NULL pointer, misaligned), WCC_ESIZE. */
+int wcc_bind(wcc_ctx* ctx, void* dev_ptr, size_t bytes, void* hip_stream);
+
+/* Copy a state in (layout above) for mesh `parity` at time t; n_cells must
+ * equal the cell count of that mesh.  Resets the half-step counter and the
+ * status flags and computes s_max on the device.  Synchronous.
+ * Errors: WCC_ESTATE (not bound), WCC_EINVAL, WCC_ESIZE, WCC_EDEVICE. */
+int wcc_write_dofs(wcc_ctx* ctx, const double* host, int64_t n_cells, int parity, double t);
+
+/* Enqueue one half-step.  dt_fixed > 0 uses that time step; otherwise
+ * dt = (cfl*dx)/s_max.  Errors: WCC_ESTATE, WCC_EINVAL, WCC_EDEVICE. */
+int wcc_step(wcc_ctx* ctx, double cfl, double dt_fixed);
+
+/* Enqueue `half_steps` CFL half-steps (no end time), replayed from captured
+ * HIP graphs of a fixed number of kernels.  Errors as wcc_step. */
+int wcc_run(wcc_ctx* ctx, int64_t half_steps, double cfl);
+
+/* Advance to t_end with CFL time steps (last one clipped), at most
+ * max_half_steps (<= 0: unlimited).  Synchronises at the end of every graph
+ * chunk to read the 16-byte status.  *taken (may be NULL) receives the
+ * half-steps done by this call.  Returns WCC_ENONFINITE if a step raised a
+ * flag (the state after that step is kept). */
+int wcc_advance(wcc_ctx* ctx, double t_end, double cfl, int64_t max_half_steps, int64_t* taken);
+
+/* Copy the current state out (layout above) into host[cap]; cap must hold
+ * nc*(P+1)*n_cells doubles.  info (may be NULL) receives time, parity, flags
+ * and sizes.  Synchronous.  Errors: WCC_ESTATE, WCC_ESIZE, WCC_EDEVICE. */
+int wcc_read_dofs(wcc_ctx* ctx, double* host, int64_t cap, wcc_state_info* info);
+
+/* Conserved totals sum_j ubar_j dx per component (cell averages from
+ * Eq. SubEq:1DCellAVG), summed in cell order on the host.  Synchronous. */
+int wcc_totals(wcc_ctx* ctx, double* per_component);
+
+/* Launch shape of the half-step kernel: threads per block (multiple of 64,
+ * <= 1024; 0 = default) and blocks (0 = enough to fill the device).  Used by
+ * the autotuner; results do not depend on it. */
+int wcc_set_launch(wcc_ctx* ctx, int threads_per_block, int blocks);
+
+/* Number of kernel launches and the device time of the last wcc_run call
+ * (HIP events around the enqueued work on the bound stream), in ms. */
+int wcc_last_run_ms(wcc_ctx* ctx, double* ms);
+
+const char* wcc_strerror(int code);
+const char* wcc_last_error(const wcc_ctx* ctx);
+void wcc_destroy(wcc_ctx* ctx);
+
+/* ------------------------------------------------------------------------
+ * Batched form: B independent instances of one equation, each with its own
+ * degree P[b] (0..3) and size N[b], same bc and params, advanced together:
+ * each half-step is ONE persistent kernel launch over a table of tiles that
+ * never straddle instances; every instance has its own time, s_max and CFL
+ * time step.  State layout per instance as above.
+ * ---------------------------------------------------------------------- */
+int wcc_batch_create(int equation, int B, const int32_t* P, const int64_t* N, int bc,
+                     const wcc_params* params, wcc_batch** out);
+int wcc_batch_workspace_bytes(const wcc_batch* bt, size_t* bytes);
+int wcc_batch_bind(wcc_batch* bt, void* dev_ptr, size_t bytes, void* hip_stream);
+/* Write instance b (parity 0, time t).  Synchronous. */
+int wcc_batch_write_dofs(wcc_batch* bt, int b, const double* host, int64_t n_cells, double t);
+/* Compute every instance's s_max after the writes (one launch).  Synchronous. */
+int wcc_batch_prepare(wcc_batch* bt);
+/* Enqueue `half_steps` half-steps of every instance; instance b uses the CFL
+ * number cfl_by_P[P[b]].  Steps are replayed from captured graphs. */
+int wcc_batch_run(wcc_batch* bt, int64_t half_steps, const double cfl_by_P[WCC_PMAX + 1]);
+/* Copy instance b out.  Synchronous. */
+int wcc_batch_read_dofs(wcc_batch* bt, int b, double* host, int64_t cap, wcc_state_info* info);
+/* Schedule of the persistent kernels: threads per block (64..256, 0 keeps the
+ * current value), blocks per launch (0 = fill the device at the kernel's
+ * occupancy) and mode (0 keeps the current one; 1 = fused: one launch per
+ * half-step over all tiles, degree switched per tile; 2 = grouped: one launch
+ * per degree per half-step).  Results do not depend on the schedule. */
+int wcc_batch_set_schedule(wcc_batch* bt, int threads_per_block, int blocks, int mode);
+int wcc_batch_last_run_ms(wcc_batch* bt, double* ms);
+const char* wcc_batch_last_error(const wcc_batch* bt);
+void wcc_batch_destroy(wcc_batch* bt);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* WCC_H */

@@ -1,0 +1,301 @@
+"""Thin Python binding of the C ABI in include/wcc.h (argument marshalling only).
+
+Every half-step runs in the gfx950 kernels of libwcc.so; PyTorch supplies the
+device workspace and the HIP stream.  There is no CPU fallback: importing this
+module without the built library, or using it without a GPU, raises.
+
+The functions keep the C names (wcc_create, wcc_step, ...); `Solver` and
+`Batch` wrap them with torch-owned device memory for convenience.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "_lib", "libwcc.so")
+
+WCC_OK, WCC_EINVAL, WCC_ESTATE, WCC_ESIZE, WCC_EDEVICE, WCC_ENONFINITE = 0, -1, -2, -3, -4, -5
+WCC_PMAX = 4
+EQUATIONS = {"advection": 0, "burgers": 1, "euler": 2}
+BCS = {"periodic": 0, "transmissive": 1, "dirichlet": 2}
+PRECISIONS = {"fp64": 0, "fp32_mixed": 1}
+
+
+class WccError(RuntimeError):
+    def __init__(self, code: int, message: str):
+        super().__init__(f"{message} (code {code})")
+        self.code = code
+
+
+class wcc_params(ctypes.Structure):
+    _fields_ = [
+        ("x_left", ctypes.c_double), ("x_right", ctypes.c_double),
+        ("a", ctypes.c_double), ("gamma", ctypes.c_double), ("eps", ctypes.c_double),
+        ("limiter", ctypes.c_int32), ("precision", ctypes.c_int32),
+        ("left_state", ctypes.c_double * 3), ("right_state", ctypes.c_double * 3),
+    ]
+
+
+class wcc_state_info(ctypes.Structure):
+    _fields_ = [
+        ("t", ctypes.c_double), ("parity", ctypes.c_int32), ("flags", ctypes.c_int32),
+        ("n_cells", ctypes.c_int64), ("x_first_center", ctypes.c_double), ("dx", ctypes.c_double),
+        ("half_steps", ctypes.c_int64), ("s_max", ctypes.c_double),
+    ]
+
+
+_c = ctypes
+_vp, _i64, _dp = _c.c_void_p, _c.c_int64, _c.POINTER(_c.c_double)
+SIGNATURES = {
+    "wcc_params_default": ([_c.POINTER(wcc_params)], _c.c_int),
+    "wcc_create": ([_c.c_int, _c.c_int, _i64, _c.c_int, _c.POINTER(wcc_params), _c.POINTER(_vp)], _c.c_int),
+    "wcc_workspace_bytes": ([_vp, _c.POINTER(_c.c_size_t)], _c.c_int),
+    "wcc_bind": ([_vp, _vp, _c.c_size_t, _vp], _c.c_int),
+    "wcc_write_dofs": ([_vp, _dp, _i64, _c.c_int, _c.c_double], _c.c_int),
+    "wcc_step": ([_vp, _c.c_double, _c.c_double], _c.c_int),
+    "wcc_run": ([_vp, _i64, _c.c_double], _c.c_int),
+    "wcc_advance": ([_vp, _c.c_double, _c.c_double, _i64, _c.POINTER(_i64)], _c.c_int),
+    "wcc_read_dofs": ([_vp, _dp, _i64, _c.POINTER(wcc_state_info)], _c.c_int),
+    "wcc_totals": ([_vp, _dp], _c.c_int),
+    "wcc_set_launch": ([_vp, _c.c_int, _c.c_int], _c.c_int),
+    "wcc_last_run_ms": ([_vp, _dp], _c.c_int),
+    "wcc_strerror": ([_c.c_int], _c.c_char_p),
+    "wcc_last_error": ([_vp], _c.c_char_p),
+    "wcc_destroy": ([_vp], None),
+    "wcc_batch_create": ([_c.c_int, _c.c_int, _c.POINTER(_c.c_int32), _c.POINTER(_i64), _c.c_int,
+                          _c.POINTER(wcc_params), _c.POINTER(_vp)], _c.c_int),
+    "wcc_batch_workspace_bytes": ([_vp, _c.POINTER(_c.c_size_t)], _c.c_int),
+    "wcc_batch_bind": ([_vp, _vp, _c.c_size_t, _vp], _c.c_int),
+    "wcc_batch_write_dofs": ([_vp, _c.c_int, _dp, _i64, _c.c_double], _c.c_int),
+    "wcc_batch_prepare": ([_vp], _c.c_int),
+    "wcc_batch_run": ([_vp, _i64, _dp], _c.c_int),
+    "wcc_batch_read_dofs": ([_vp, _c.c_int, _dp, _i64, _c.POINTER(wcc_state_info)], _c.c_int),
+    "wcc_batch_set_schedule": ([_vp, _c.c_int, _c.c_int, _c.c_int], _c.c_int),
+    "wcc_batch_last_run_ms": ([_vp, _dp], _c.c_int),
+    "wcc_batch_last_error": ([_vp], _c.c_char_p),
+    "wcc_batch_destroy": ([_vp], None),
+}
+
+_lib = None
+
+
+def load(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load libwcc.so (no GPU needed to load; every compute call needs one)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with paper_2104_04347_amd/build.py "
+                           "(the HIP library is the only implementation)")
+    # PyTorch first: libwcc.so links the HIP runtime bundled with PyTorch, and
+    # torch's memory, streams and events must be those of the same runtime.
+    import torch  # noqa: F401
+    lib = ctypes.CDLL(path)
+    for name, (argtypes, restype) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.argtypes = argtypes
+        fn.restype = restype
+    _lib = lib
+    return lib
+
+
+def _dptr(a: np.ndarray):
+    return a.ctypes.data_as(_dp)
+
+
+def _check(rc: int, what: str, ctx=None, batch=False):
+    if rc != WCC_OK:
+        lib = load()
+        detail = ""
+        if ctx is not None:
+            detail = (lib.wcc_batch_last_error(ctx) if batch else lib.wcc_last_error(ctx)) or b""
+            detail = detail.decode(errors="replace")
+        raise WccError(rc, f"{what}: {lib.wcc_strerror(rc).decode()}" + (f" -- {detail}" if detail else ""))
+
+
+def make_params(limiter=True, precision="fp64", x_left=0.0, x_right=1.0, a=1.0, gamma=1.4, eps=1e-40,
+                left_state=(0.0, 0.0, 0.0), right_state=(0.0, 0.0, 0.0)) -> wcc_params:
+    p = wcc_params()
+    load().wcc_params_default(ctypes.byref(p))
+    p.x_left, p.x_right, p.a, p.gamma, p.eps = x_left, x_right, a, gamma, eps
+    p.limiter = 1 if limiter else 0
+    p.precision = PRECISIONS[precision]
+    for i in range(3):
+        p.left_state[i] = float(left_state[i]) if i < len(left_state) else 0.0
+        p.right_state[i] = float(right_state[i]) if i < len(right_state) else 0.0
+    return p
+
+
+def _torch_device_buffer(nbytes: int):
+    import torch
+    if not torch.cuda.is_available():
+        raise RuntimeError("no GPU visible: the WCC library runs only on the GPU")
+    # 256-byte alignment: the caching allocator returns 512-byte aligned blocks
+    buf = torch.empty(max(nbytes, 256), dtype=torch.uint8, device="cuda")
+    assert buf.data_ptr() % 256 == 0
+    return buf
+
+
+def _torch_stream_handle():
+    import torch
+    return torch.cuda.current_stream().cuda_stream
+
+
+class Solver:
+    """One instance: u_t + f(u)_x = 0 advanced by the gfx950 half-step kernel."""
+
+    def __init__(self, equation: str, P: int, N: int, bc: str = "periodic", *, limiter: bool = True,
+                 precision: str = "fp64", x_left: float = 0.0, x_right: float = 1.0, a: float = 1.0,
+                 gamma: float = 1.4, eps: float = 1e-40, left_state=(0.0, 0.0, 0.0),
+                 right_state=(0.0, 0.0, 0.0), stream=None):
+        lib = load()
+        self.equation, self.P, self.N, self.bc = equation, P, N, bc
+        self.nc = 3 if equation == "euler" else 1
+        self.params = make_params(limiter, precision, x_left, x_right, a, gamma, eps, left_state, right_state)
+        h = ctypes.c_void_p()
+        _check(lib.wcc_create(EQUATIONS[equation], P, N, BCS[bc], ctypes.byref(self.params), ctypes.byref(h)),
+               "wcc_create")
+        self.h = h
+        nb = ctypes.c_size_t()
+        _check(lib.wcc_workspace_bytes(h, ctypes.byref(nb)), "wcc_workspace_bytes", h)
+        self.workspace = _torch_device_buffer(nb.value)
+        self.stream = stream if stream is not None else _torch_stream_handle()
+        _check(lib.wcc_bind(h, ctypes.c_void_p(self.workspace.data_ptr()), nb.value, ctypes.c_void_p(self.stream)),
+               "wcc_bind", h)
+
+    def ncells(self, parity: int) -> int:
+        if self.bc == "periodic":
+            return self.N
+        return self.N + 1 if parity % 2 == 0 else self.N
+
+    def write(self, q: np.ndarray, parity: int = 0, t: float = 0.0) -> None:
+        q = np.ascontiguousarray(q, dtype=np.float64)
+        n = self.ncells(parity)
+        assert q.shape == (self.nc, self.P + 1, n), (q.shape, (self.nc, self.P + 1, n))
+        _check(load().wcc_write_dofs(self.h, _dptr(q), n, parity, float(t)), "wcc_write_dofs", self.h)
+
+    def step(self, cfl: float = 0.0, dt_fixed: float = 0.0) -> None:
+        _check(load().wcc_step(self.h, float(cfl), float(dt_fixed)), "wcc_step", self.h)
+
+    def run(self, half_steps: int, cfl: float) -> None:
+        _check(load().wcc_run(self.h, int(half_steps), float(cfl)), "wcc_run", self.h)
+
+    def advance(self, t_end: float, cfl: float, max_half_steps: int = 0) -> int:
+        taken = ctypes.c_int64()
+        _check(load().wcc_advance(self.h, float(t_end), float(cfl), int(max_half_steps), ctypes.byref(taken)),
+               "wcc_advance", self.h)
+        return taken.value
+
+    def info(self) -> wcc_state_info:
+        inf = wcc_state_info()
+        _check(load().wcc_read_dofs(self.h, None, 0, ctypes.byref(inf)), "wcc_read_dofs", self.h)
+        return inf
+
+    def read(self):
+        inf = self.info()
+        n = inf.n_cells
+        out = np.empty((self.nc, self.P + 1, n), dtype=np.float64)
+        _check(load().wcc_read_dofs(self.h, _dptr(out), out.size, ctypes.byref(inf)), "wcc_read_dofs", self.h)
+        return out, inf
+
+    def totals(self) -> np.ndarray:
+        out = np.zeros(self.nc)
+        _check(load().wcc_totals(self.h, _dptr(out)), "wcc_totals", self.h)
+        return out
+
+    def set_launch(self, threads: int = 0, blocks: int = 0) -> None:
+        _check(load().wcc_set_launch(self.h, int(threads), int(blocks)), "wcc_set_launch", self.h)
+
+    def last_run_ms(self) -> float:
+        ms = ctypes.c_double()
+        _check(load().wcc_last_run_ms(self.h, ctypes.byref(ms)), "wcc_last_run_ms", self.h)
+        return ms.value
+
+    def close(self):
+        if getattr(self, "h", None):
+            load().wcc_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Many independent instances advanced together by persistent kernels."""
+
+    def __init__(self, equation: str, P, N, bc: str = "transmissive", *, limiter: bool = True,
+                 precision: str = "fp32_mixed", x_left: float = 0.0, x_right: float = 1.0, a: float = 1.0,
+                 gamma: float = 1.4, eps: float = 1e-40, stream=None):
+        lib = load()
+        self.P = np.ascontiguousarray(P, dtype=np.int32)
+        self.N = np.ascontiguousarray(N, dtype=np.int64)
+        self.B = int(self.P.size)
+        self.bc = bc
+        self.nc = 3 if equation == "euler" else 1
+        self.params = make_params(limiter, precision, x_left, x_right, a, gamma, eps)
+        h = ctypes.c_void_p()
+        _check(lib.wcc_batch_create(EQUATIONS[equation], self.B,
+                                    self.P.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                    self.N.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), BCS[bc],
+                                    ctypes.byref(self.params), ctypes.byref(h)), "wcc_batch_create")
+        self.h = h
+        nb = ctypes.c_size_t()
+        _check(lib.wcc_batch_workspace_bytes(h, ctypes.byref(nb)), "wcc_batch_workspace_bytes", h, True)
+        self.workspace = _torch_device_buffer(nb.value)
+        self.stream = stream if stream is not None else _torch_stream_handle()
+        _check(lib.wcc_batch_bind(h, ctypes.c_void_p(self.workspace.data_ptr()), nb.value,
+                                  ctypes.c_void_p(self.stream)), "wcc_batch_bind", h, True)
+
+    def ncells(self, b: int, parity: int) -> int:
+        if self.bc == "periodic":
+            return int(self.N[b])
+        return int(self.N[b]) + 1 if parity % 2 == 0 else int(self.N[b])
+
+    def write(self, b: int, q: np.ndarray, t: float = 0.0) -> None:
+        q = np.ascontiguousarray(q, dtype=np.float64)
+        assert q.shape == (self.nc, int(self.P[b]) + 1, self.ncells(b, 0))
+        _check(load().wcc_batch_write_dofs(self.h, int(b), _dptr(q), q.shape[2], float(t)),
+               "wcc_batch_write_dofs", self.h, True)
+
+    def prepare(self) -> None:
+        _check(load().wcc_batch_prepare(self.h), "wcc_batch_prepare", self.h, True)
+
+    def run(self, half_steps: int, cfl_by_P) -> None:
+        c = np.zeros(WCC_PMAX + 1)
+        c[: len(cfl_by_P)] = cfl_by_P
+        _check(load().wcc_batch_run(self.h, int(half_steps), _dptr(c)), "wcc_batch_run", self.h, True)
+
+    def read(self, b: int):
+        inf = wcc_state_info()
+        _check(load().wcc_batch_read_dofs(self.h, int(b), None, 0, ctypes.byref(inf)), "wcc_batch_read_dofs",
+               self.h, True)
+        out = np.empty((self.nc, int(self.P[b]) + 1, inf.n_cells))
+        _check(load().wcc_batch_read_dofs(self.h, int(b), _dptr(out), out.size, ctypes.byref(inf)),
+               "wcc_batch_read_dofs", self.h, True)
+        return out, inf
+
+    def set_schedule(self, threads: int = 0, blocks: int = 0, mode: int = 0) -> None:
+        _check(load().wcc_batch_set_schedule(self.h, int(threads), int(blocks), int(mode)),
+               "wcc_batch_set_schedule", self.h, True)
+
+    def last_run_ms(self) -> float:
+        ms = ctypes.c_double()
+        _check(load().wcc_batch_last_run_ms(self.h, ctypes.byref(ms)), "wcc_batch_last_run_ms", self.h, True)
+        return ms.value
+
+    def close(self):
+        if getattr(self, "h", None):
+            load().wcc_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,163 @@
+// wcc_kernels.hip -- the fused WCC half-step kernels for gfx950 (MI355X).
+//
+// One launch = one half-step of one instance (Section 2.1 of Shen & Parsani,
+// arXiv:2104.04347).  Work decomposition:
+//   * a wavefront owns a tile of 64 consecutive OLD cells and produces the 63
+//     NEW cells whose two parents both lie in the tile (one old cell of
+//     overlap between neighbouring tiles: 1/64 redundant expansion work);
+//   * every lane expands its own old cell (Cauchy-Kovalewski in registers),
+//     then takes the right parent's half of the interface data from lane+1
+//     with DPP wave_shl:1 row moves -- no LDS, no barrier;
+//   * a block owns a contiguous run of tiles (its waves walk it four apart),
+//     so neighbouring tiles share cache lines inside one CU / XCD;
+//   * the state is structure of arrays: point values [c][j] in binary64 and
+//     derivatives [c][k-1][j] in the bulk type, rows padded to 64 cells, so
+//     every load and store of a wave is a contiguous 256/512-byte segment.
+// Time control is on the device: the kernel reads t and s_max from a ring of
+// three slots, writes the next time to the next slot, max-reduces its wave
+// speeds into the next slot and clears the slot after that, so consecutive
+// launches (and captured graphs of them) need no host round trip.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "wcc_cell.hpp"
+#include "wcc_internal.hpp"
+#include "wcc_tile.hpp"
+
+namespace wcc {
+
+template <int EQ, int P, bool LIM, class R>
+__global__ __launch_bounds__(256) void k_half_step(const StepArgs<R> a) {
+  double dt;
+  if (!step_time(a.ctrl, a.slot, a.dx, a.dt_fixed, blockIdx.x == 0 && threadIdx.x == 0, dt)) return;
+  const double lam = dt / a.dx;
+  const R nlam = (R)(-lam);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int64_t tiles = (a.n_new + 62) / 63;
+  const int64_t per_block = (tiles + gridDim.x - 1) / gridDim.x;
+  const int64_t t_begin = (int64_t)blockIdx.x * per_block;
+  const int64_t t_stop = t_begin + per_block < tiles ? t_begin + per_block : tiles;
+  double smax = 0.0;
+  unsigned flags = 0u;
+  for (int64_t tile = t_begin + wave; tile < t_stop; tile += nw)
+    run_tile<EQ, P, LIM, R>(a, tile, lam, nlam, lane, smax, flags);
+  publish(a.ctrl, a.slot, smax, flags);
+}
+
+// Largest wave speed of the stored state (first time step after a write).
+template <int EQ, int P, class R>
+__global__ __launch_bounds__(256) void k_state_speed(const StepArgs<R> a) {
+  constexpr int NC = ncomp<EQ>();
+  double smax = 0.0;
+  unsigned flags = 0u;
+  const int64_t n = a.n_old;
+  for (int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; o < n; o += (int64_t)gridDim.x * blockDim.x) {
+    double p[NC];
+    R d[NC][P + 1];
+    load_cell<EQ, P, R>(a.p_old, a.d_old, a.ld, o, 0, a, p, d);
+    const double sp = stored_speed<EQ, P, R>(p, d, a.ph);
+    smax = __builtin_fmax(smax, sp);
+    if (!(sp == sp)) flags |= 1u;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      bool ok = __builtin_isfinite(p[c]);
+#pragma unroll
+      for (int k = 1; k <= P; ++k) ok = ok && finiteT(d[c][k]);
+      if (!ok) flags |= 1u;
+    }
+  }
+  // publish into the CURRENT slot: pass slot-1 so that publish's "next" is slot
+  publish(a.ctrl, a.slot == 0 ? 2 : a.slot - 1, smax, flags);
+}
+
+// ---------------------------------------------------------------------------
+// Host-side dispatch over the compile-time variants.
+// ---------------------------------------------------------------------------
+template <int EQ, int P, bool LIM, class R>
+static hipError_t launch_one(const StepArgs<R>& a, int blocks, int threads, hipStream_t s) {
+  hipLaunchKernelGGL((k_half_step<EQ, P, LIM, R>), dim3(blocks), dim3(threads), 0, s, a);
+  return hipGetLastError();
+}
+
+template <int EQ, int P, class R>
+static hipError_t launch_lim(const StepArgs<R>& a, bool lim, int blocks, int threads, hipStream_t s) {
+  if (lim && P >= 1) return launch_one<EQ, P, true, R>(a, blocks, threads, s);
+  return launch_one<EQ, P, false, R>(a, blocks, threads, s);
+}
+
+template <int EQ, class R>
+static hipError_t launch_p(const StepArgs<R>& a, int P, bool lim, int blocks, int threads, hipStream_t s) {
+  switch (P) {
+    case 0: return launch_lim<EQ, 0, R>(a, false, blocks, threads, s);
+    case 1: return launch_lim<EQ, 1, R>(a, lim, blocks, threads, s);
+    case 2: return launch_lim<EQ, 2, R>(a, lim, blocks, threads, s);
+    case 3: return launch_lim<EQ, 3, R>(a, lim, blocks, threads, s);
+    case 4: return launch_lim<EQ, 4, R>(a, lim, blocks, threads, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <class R>
+hipError_t launch_half_step(const StepArgs<R>& a, int eq, int P, bool lim, int blocks, int threads, hipStream_t s) {
+  switch (eq) {
+    case kAdvection: return launch_p<kAdvection, R>(a, P, lim, blocks, threads, s);
+    case kBurgers: return launch_p<kBurgers, R>(a, P, lim, blocks, threads, s);
+    case kEuler: return launch_p<kEuler, R>(a, P, lim, blocks, threads, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <int EQ, class R>
+static hipError_t launch_speed_p(const StepArgs<R>& a, int P, int blocks, hipStream_t s) {
+  switch (P) {
+    case 0: hipLaunchKernelGGL((k_state_speed<EQ, 0, R>), dim3(blocks), dim3(256), 0, s, a); break;
+    case 1: hipLaunchKernelGGL((k_state_speed<EQ, 1, R>), dim3(blocks), dim3(256), 0, s, a); break;
+    case 2: hipLaunchKernelGGL((k_state_speed<EQ, 2, R>), dim3(blocks), dim3(256), 0, s, a); break;
+    case 3: hipLaunchKernelGGL((k_state_speed<EQ, 3, R>), dim3(blocks), dim3(256), 0, s, a); break;
+    case 4: hipLaunchKernelGGL((k_state_speed<EQ, 4, R>), dim3(blocks), dim3(256), 0, s, a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <class R>
+hipError_t launch_state_speed(const StepArgs<R>& a, int eq, int P, int blocks, hipStream_t s) {
+  switch (eq) {
+    case kAdvection: return launch_speed_p<kAdvection, R>(a, P, blocks, s);
+    case kBurgers: return launch_speed_p<kBurgers, R>(a, P, blocks, s);
+    case kEuler: return launch_speed_p<kEuler, R>(a, P, blocks, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <class R>
+hipError_t occupancy_half_step(int eq, int P, bool lim, int threads, int* blocks_per_cu) {
+  // Queried for the heaviest variant that can run; the kernel is the same for
+  // every equation except in register use, so ask for the exact one.
+  const void* f = nullptr;
+#define WCC_K(E, PP, L) reinterpret_cast<const void*>(&k_half_step<E, PP, L, R>)
+#define WCC_PSWITCH(E)                                                            \
+  switch (P) {                                                                    \
+    case 0: f = WCC_K(E, 0, false); break;                                        \
+    case 1: f = lim ? WCC_K(E, 1, true) : WCC_K(E, 1, false); break;              \
+    case 2: f = lim ? WCC_K(E, 2, true) : WCC_K(E, 2, false); break;              \
+    case 3: f = lim ? WCC_K(E, 3, true) : WCC_K(E, 3, false); break;              \
+    case 4: f = lim ? WCC_K(E, 4, true) : WCC_K(E, 4, false); break;              \
+  }
+  if (eq == kAdvection) { WCC_PSWITCH(kAdvection) }
+  else if (eq == kBurgers) { WCC_PSWITCH(kBurgers) }
+  else { WCC_PSWITCH(kEuler) }
+#undef WCC_PSWITCH
+#undef WCC_K
+  if (!f) return hipErrorInvalidValue;
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, f, threads, 0);
+}
+
+template hipError_t launch_half_step<double>(const StepArgs<double>&, int, int, bool, int, int, hipStream_t);
+template hipError_t launch_half_step<float>(const StepArgs<float>&, int, int, bool, int, int, hipStream_t);
+template hipError_t launch_state_speed<double>(const StepArgs<double>&, int, int, int, hipStream_t);
+template hipError_t launch_state_speed<float>(const StepArgs<float>&, int, int, int, hipStream_t);
+template hipError_t occupancy_half_step<double>(int, int, bool, int, int*);
+template hipError_t occupancy_half_step<float>(int, int, bool, int, int*);
+
+}  // namespace wcc

@@ -1,0 +1,198 @@
+// wcc_tile.hpp -- wave-level building blocks shared by the single-instance and
+// batched half-step kernels: lane exchange by DPP, wave/block reductions, the
+// device-side time step and the body that turns one tile of 64 old cells into
+// 63 new cells.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "wcc_cell.hpp"
+#include "wcc_internal.hpp"
+
+namespace wcc {
+
+// wave_shl:1 -- lane i receives lane i+1 (lane 63 receives `old`).
+__device__ __forceinline__ int dpp_from_next(int x) { return __builtin_amdgcn_update_dpp(0, x, 0x130, 0xF, 0xF, false); }
+__device__ __forceinline__ float dpp_from_next(float x) {
+  return __int_as_float(dpp_from_next(__float_as_int(x)));
+}
+__device__ __forceinline__ double dpp_from_next(double x) {
+  const long long v = __double_as_longlong(x);
+  const int lo = dpp_from_next((int)(v & 0xffffffffll));
+  const int hi = dpp_from_next((int)(v >> 32));
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v = __builtin_fmax(v, __shfl_xor(v, o));
+  return v;
+}
+__device__ __forceinline__ unsigned wave_or(unsigned v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v |= (unsigned)__shfl_xor((int)v, o);
+  return v;
+}
+
+// Time-step bookkeeping shared by the single and batched kernels.  Returns
+// false when this launch must do nothing (end time reached or a flag raised
+// by an earlier step); in that case the slot is propagated unchanged.
+__device__ __forceinline__ bool step_time(Ctrl* ctrl, int slot, double dx, double dt_fixed, bool leader,
+                                          double& dt) {
+  const int s1 = slot == 2 ? 0 : slot + 1;
+  const int s2 = s1 == 2 ? 0 : s1 + 1;
+  const double t = ctrl->t[slot];
+  const unsigned flags_in = ctrl->flags[slot];
+  bool done = flags_in != 0u;
+  double tn;
+  if (dt_fixed > 0.0) {
+    dt = dt_fixed;
+    tn = t + dt;
+  } else {
+    const double smax = __longlong_as_double((long long)ctrl->smax[slot]);
+    const double tend = ctrl->t_end;
+    done = done || !(t < tend);
+    dt = (ctrl->cfl * dx) / smax;
+    const double rem = tend - t;
+    if (dt >= rem) {
+      dt = rem;
+      tn = tend;
+    } else {
+      tn = t + dt;
+    }
+  }
+  if (leader) {
+    if (done) {
+      ctrl->t[s1] = t;
+      ctrl->smax[s1] = ctrl->smax[slot];
+      ctrl->flags[s1] = flags_in;
+    } else {
+      ctrl->t[s1] = tn;
+      ctrl->steps_done += 1;
+    }
+    ctrl->smax[s2] = 0ull;
+    ctrl->flags[s2] = 0u;
+  }
+  return !done;
+}
+
+// Per-block reduction of the wave speeds and flags, then one atomic each,
+// skipped when it cannot raise the stored maximum.
+__device__ __forceinline__ void publish(Ctrl* ctrl, int slot, double smax, unsigned flags) {
+  __shared__ double red_s[16];
+  __shared__ unsigned red_f[16];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  smax = wave_max(smax);
+  flags = wave_or(flags);
+  if (lane == 0) {
+    red_s[wave] = smax;
+    red_f[wave] = flags;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < nw; ++w) {
+      smax = __builtin_fmax(smax, red_s[w]);
+      flags |= red_f[w];
+    }
+    const int s1 = slot == 2 ? 0 : slot + 1;
+    const unsigned long long bits = (unsigned long long)__double_as_longlong(smax);
+    if (bits > __hip_atomic_load(&ctrl->smax[s1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+      atomicMax(&ctrl->smax[s1], bits);
+    if (flags) atomicOr(&ctrl->flags[s1], flags);
+  }
+}
+
+// Load the old cell `o` (already mapped into [0, n_old)), or a Dirichlet ghost.
+template <int EQ, int P, class R>
+__device__ __forceinline__ void load_cell(const double* __restrict__ pv, const R* __restrict__ dv, int64_t ld,
+                                          int64_t o, int ghost, const StepArgs<R>& a,
+                                          double (&p)[ncomp<EQ>()], R (&d)[ncomp<EQ>()][P + 1]) {
+  constexpr int NC = ncomp<EQ>();
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    p[c] = pv[c * ld + o];
+    d[c][0] = (R)0;
+#pragma unroll
+    for (int k = 1; k <= P; ++k) d[c][k] = dv[(c * P + (k - 1)) * ld + o];
+  }
+  if (ghost) {
+    const double* g = a.ctrl->ghost[ghost - 1];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      p[c] = g[c];
+#pragma unroll
+      for (int k = 1; k <= P; ++k) d[c][k] = (R)0;
+    }
+  }
+}
+
+// Map the lane's old-cell index onto storage: periodic wrap, transmissive
+// copies of the end cells for the ghosts of the odd->even step, Dirichlet
+// ghost states, clamping for lanes past the end (their results are unused).
+__device__ __forceinline__ int64_t map_old(int64_t o, int64_t n_old, int64_t N, int bc, int parity_old,
+                                           int& ghost) {
+  ghost = 0;
+  if (bc == kPeriodic) {
+    o %= N;
+    if (o < 0) o += N;
+    return o;
+  }
+  if (o < 0) {
+    if (bc == kDirichlet && parity_old == 1) ghost = 1;
+    return 0;
+  }
+  if (o >= n_old) {
+    if (bc == kDirichlet && parity_old == 1 && o == n_old) ghost = 2;
+    return n_old - 1;
+  }
+  return o;
+}
+
+template <int EQ, int P, bool LIM, class R>
+__device__ __forceinline__ void run_tile(const StepArgs<R>& a, int64_t tile, double lam, R nlam, int lane,
+                                         double& smax, unsigned& flags) {
+  constexpr int NC = ncomp<EQ>();
+  constexpr int PV = P > 0 ? P : 1;
+  const int64_t j0 = tile * 63;
+  int ghost;
+  const int64_t o = map_old(j0 + lane - (a.parity_old == 1 ? 1 : 0), a.n_old, a.N, a.bc, a.parity_old, ghost);
+  double p[NC];
+  R d[NC][P + 1];
+  load_cell<EQ, P, R>(a.p_old, a.d_old, a.ld, o, ghost, a, p, d);
+
+  OldOut<EQ, P, R> X;
+  old_cell<EQ, P, R>(p, d, nlam, a.ph, X);
+  __builtin_amdgcn_sched_barrier(0);
+
+  // Right parent's half of the interface data from lane + 1.
+  double uL_R[NC];
+  R fbar_R[NC];
+  R V_R[NC][PV];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    uL_R[c] = dpp_from_next(X.uL[c]);
+    fbar_R[c] = dpp_from_next(X.fbar[c]);
+#pragma unroll
+    for (int k = 0; k < P; ++k) V_R[c][k] = dpp_from_next(X.V[c][k]);
+    if (P == 0) V_R[c][0] = (R)0;
+  }
+
+  const int64_t j = j0 + lane;
+  if (lane < 63 && j < a.n_new) {
+    double pn[NC];
+    R dn[NC][P + 1];
+    double sp;
+    flags |= (unsigned)new_cell<EQ, P, LIM, R>(X, uL_R, fbar_R, V_R, lam, a.ph, pn, dn, sp);
+    smax = __builtin_fmax(smax, sp);
+    if (!(sp == sp)) smax = sp;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      a.p_new[c * a.ld + j] = pn[c];
+#pragma unroll
+      for (int k = 1; k <= P; ++k) a.d_new[(c * P + (k - 1)) * a.ld + j] = dn[c][k];
+    }
+  }
+}
+
+}  // namespace wcc

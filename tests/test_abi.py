@@ -1,0 +1,95 @@
+"""CPU checks of the boundary: the HIP library loads, exports every symbol that
+include/wcc.h declares, and validates arguments in the calls that need no GPU."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2104_04347_amd import binding
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "wcc.h")
+
+
+def declared():
+    txt = open(HEADER).read()
+    return sorted(set(re.findall(r"^(?:int|void|const char\*)\s+(wcc_\w+)\s*\(", txt, re.M)))
+
+
+def test_header_declares_the_abi():
+    names = declared()
+    assert "wcc_create" in names and "wcc_batch_run" in names and len(names) >= 20
+
+
+def test_library_exports_every_declared_symbol():
+    lib = binding.load()
+    for name in declared():
+        assert hasattr(lib, name), name
+    assert set(declared()) == set(binding.SIGNATURES), set(declared()) ^ set(binding.SIGNATURES)
+
+
+def test_error_strings():
+    lib = binding.load()
+    for code in (0, -1, -2, -3, -4, -5):
+        assert lib.wcc_strerror(code)
+    assert b"unknown" in lib.wcc_strerror(-99)
+
+
+def test_create_rejects_bad_arguments():
+    lib = binding.load()
+    h = ctypes.c_void_p()
+    p = binding.make_params()
+    for eq, P, N, bc in [(3, 2, 100, 0), (0, 5, 100, 0), (0, -1, 100, 0), (0, 2, 1, 0), (0, 2, 100, 3)]:
+        assert lib.wcc_create(eq, P, N, bc, ctypes.byref(p), ctypes.byref(h)) == binding.WCC_EINVAL
+    bad = binding.make_params(x_left=1.0, x_right=0.0)
+    assert lib.wcc_create(0, 2, 100, 0, ctypes.byref(bad), ctypes.byref(h)) == binding.WCC_EINVAL
+    bad = binding.make_params(gamma=1.0)
+    assert lib.wcc_create(2, 2, 100, 0, ctypes.byref(bad), ctypes.byref(h)) == binding.WCC_EINVAL
+
+
+def test_workspace_size_and_state_errors_without_gpu():
+    lib = binding.load()
+    h = ctypes.c_void_p()
+    p = binding.make_params(precision="fp64")
+    assert lib.wcc_create(2, 3, 1 << 20, 1, ctypes.byref(p), ctypes.byref(h)) == 0
+    nb = ctypes.c_size_t()
+    assert lib.wcc_workspace_bytes(h, ctypes.byref(nb)) == 0
+    ld = ((1 << 20) + 1 + 63) // 64 * 64
+    assert nb.value >= 2 * 3 * 4 * ld * 8          # two buffers of 3 components x (P+1) doubles
+    # calls before bind are refused without touching the device
+    assert lib.wcc_step(h, ctypes.c_double(0.25), ctypes.c_double(0.0)) == binding.WCC_ESTATE
+    assert lib.wcc_run(h, 10, ctypes.c_double(0.25)) == binding.WCC_ESTATE
+    assert lib.wcc_bind(h, None, 0, None) == binding.WCC_EINVAL
+    assert lib.wcc_bind(h, ctypes.c_void_p(256), 16, None) == binding.WCC_ESIZE
+    assert lib.wcc_bind(h, ctypes.c_void_p(255), nb.value, None) == binding.WCC_EINVAL
+    lib.wcc_destroy(h)
+    pm = binding.make_params(precision="fp32_mixed")
+    assert lib.wcc_create(2, 3, 1 << 20, 1, ctypes.byref(pm), ctypes.byref(h)) == 0
+    nm = ctypes.c_size_t()
+    lib.wcc_workspace_bytes(h, ctypes.byref(nm))
+    assert nm.value < nb.value                      # binary32 derivatives
+    lib.wcc_destroy(h)
+
+
+def test_batch_create_validates():
+    lib = binding.load()
+    h = ctypes.c_void_p()
+    p = binding.make_params(precision="fp32_mixed")
+    P = (ctypes.c_int32 * 3)(1, 2, 3)
+    N = (ctypes.c_int64 * 3)(300, 1000, 70)
+    assert lib.wcc_batch_create(2, 3, P, N, 1, ctypes.byref(p), ctypes.byref(h)) == 0
+    nb = ctypes.c_size_t()
+    assert lib.wcc_batch_workspace_bytes(h, ctypes.byref(nb)) == 0 and nb.value > 0
+    assert lib.wcc_batch_set_schedule(h, 100, 0, 0) == binding.WCC_EINVAL
+    assert lib.wcc_batch_set_schedule(h, 128, 64, 1) == 0
+    lib.wcc_batch_destroy(h)
+    Pbad = (ctypes.c_int32 * 3)(1, 4, 3)
+    assert lib.wcc_batch_create(2, 3, Pbad, N, 1, ctypes.byref(p), ctypes.byref(h)) == binding.WCC_EINVAL
+
+
+def test_product_path_has_no_cpu_fallback(monkeypatch):
+    """Without the built library the binding fails loudly."""
+    monkeypatch.setattr(binding, "_lib", None)
+    with pytest.raises(RuntimeError):
+        binding.load("/nonexistent/libwcc.so")
