@@ -1,0 +1,136 @@
+"""Launch-shape autotuner for the WCC half-step kernels.
+
+Results never depend on the launch shape (every tile runs the same per-cell
+arithmetic; the batched kernels are checked bit for bit against
+single-instance runs in both schedules), so the tuner only measures time:
+
+* single instance: threads per block (64..256) x blocks per launch
+  (multiples of the device's resident-block capacity);
+* batched: schedule mode (fused: one launch per half-step switching on the
+  degree per tile; grouped: one launch per degree) x threads x blocks.
+
+Each candidate is timed with HIP events around graph-replayed half-steps on
+the caller's stream, after a warm-up; the best shape is cached in a JSON file
+(``$WCC_AUTOTUNE_CACHE``, default ``~/.cache/wcc_autotune.json``) keyed by
+equation, degree, precision, limiter and a power-of-two size bucket.
+"""
+from __future__ import annotations
+
+import json
+import os
+import time
+
+import numpy as np
+
+from . import binding
+
+
+def cache_path() -> str:
+    return os.environ.get("WCC_AUTOTUNE_CACHE", os.path.join(os.path.expanduser("~"), ".cache",
+                                                             "wcc_autotune.json"))
+
+
+def _load_cache() -> dict:
+    try:
+        with open(cache_path()) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def _save_cache(c: dict) -> None:
+    p = cache_path()
+    os.makedirs(os.path.dirname(p), exist_ok=True)
+    tmp = p + ".tmp"
+    with open(tmp, "w") as f:
+        json.dump(c, f, indent=1, sort_keys=True)
+    os.replace(tmp, p)
+
+
+def key_single(equation: str, P: int, N: int, precision: str, limiter: bool) -> str:
+    return f"single/{equation}/P{P}/{precision}/{'lim' if limiter else 'nolim'}/N2^{int(np.log2(max(N, 2)))}"
+
+
+def tune_single(solver: "binding.Solver", q0: np.ndarray, cfl: float, steps: int = 96,
+                threads=(64, 128, 256), block_factors=(0.5, 1, 2, 4, 8), verbose: bool = False) -> dict:
+    """Time the candidate shapes on `solver` (state q0, CFL cfl); keep the best."""
+    import torch
+    cu = torch.cuda.get_device_properties(0).multi_processor_count
+    results = []
+    for th in threads:
+        for bf in block_factors:
+            blocks = max(1, int(round(bf * cu)))
+            solver.set_launch(th, blocks)
+            solver.write(q0)
+            solver.run(48, cfl)            # warm-up, builds the graphs of this shape
+            torch.cuda.synchronize()
+            solver.run(steps, cfl)
+            ms = solver.last_run_ms()
+            results.append({"threads": th, "blocks": blocks, "ms_per_step": ms / steps})
+            if verbose:
+                print(f"  threads={th:4d} blocks={blocks:6d}: {ms / steps * 1e3:8.2f} us/half-step", flush=True)
+    solver.set_launch(0, 0)
+    solver.write(q0)
+    solver.run(48, cfl)
+    torch.cuda.synchronize()
+    solver.run(steps, cfl)
+    default_ms = solver.last_run_ms() / steps
+    best = min(results, key=lambda r: r["ms_per_step"])
+    if default_ms <= best["ms_per_step"]:
+        best = {"threads": 0, "blocks": 0, "ms_per_step": default_ms}
+    best["default_ms_per_step"] = default_ms
+    best["tried"] = results
+    c = _load_cache()
+    c[key_single(solver.equation, solver.P, solver.N, binding.PRECISIONS_NAME[solver.params.precision],
+                 bool(solver.params.limiter))] = {k: best[k] for k in ("threads", "blocks", "ms_per_step")}
+    _save_cache(c)
+    solver.set_launch(best["threads"], best["blocks"])
+    return best
+
+
+def apply_single(solver: "binding.Solver") -> bool:
+    """Apply a cached shape to `solver` if one exists; returns whether it did."""
+    k = key_single(solver.equation, solver.P, solver.N, binding.PRECISIONS_NAME[solver.params.precision],
+                   bool(solver.params.limiter))
+    c = _load_cache().get(k)
+    if not c:
+        return False
+    solver.set_launch(c["threads"], c["blocks"])
+    return True
+
+
+def tune_batch(batch: "binding.Batch", states: list, cfl_by_P, steps: int = 24, modes=(1, 2),
+               threads=(128, 256), block_factors=(0, 1, 2, 4), verbose: bool = False) -> dict:
+    """Time batched schedules.  `states` are the instances' initial states; the
+    batch is rewritten before every candidate (a fresh bind restarts time)."""
+    import torch
+    cu = torch.cuda.get_device_properties(0).multi_processor_count
+    results = []
+    for mode in modes:
+        for th in threads:
+            for bf in block_factors:
+                blocks = 0 if bf == 0 else max(1, int(round(bf * cu)))
+                batch.set_schedule(th, blocks, mode)
+                batch.rebind()
+                for b, q in enumerate(states):
+                    batch.write(b, q)
+                batch.prepare()
+                batch.run(steps, cfl_by_P)          # warm-up, builds graphs
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                batch.run(steps, cfl_by_P)
+                torch.cuda.synchronize()
+                wall = time.perf_counter() - t0
+                ms = batch.last_run_ms()
+                results.append({"mode": mode, "threads": th, "blocks": blocks, "ms_per_step": ms / steps,
+                                "wall_ms_per_step": wall * 1e3 / steps})
+                if verbose:
+                    print(f"  mode={mode} threads={th} blocks={blocks}: {ms / steps:.3f} ms/half-step", flush=True)
+    best = min(results, key=lambda r: r["ms_per_step"])
+    batch.set_schedule(best["threads"], best["blocks"], best["mode"])
+    c = _load_cache()
+    c[f"batch/B{batch.B}/{binding.PRECISIONS_NAME[batch.params.precision]}"] = {
+        k: best[k] for k in ("mode", "threads", "blocks", "ms_per_step")}
+    _save_cache(c)
+    best["tried"] = results
+    return best

@@ -22,6 +22,7 @@ WCC_PMAX = 4
 EQUATIONS = {"advection": 0, "burgers": 1, "euler": 2}
 BCS = {"periodic": 0, "transmissive": 1, "dirichlet": 2}
 PRECISIONS = {"fp64": 0, "fp32_mixed": 1}
+PRECISIONS_NAME = {v: k for k, v in PRECISIONS.items()}
 
 
 class WccError(RuntimeError):
@@ -251,6 +252,12 @@ class Batch:
         self.stream = stream if stream is not None else _torch_stream_handle()
         _check(lib.wcc_batch_bind(h, ctypes.c_void_p(self.workspace.data_ptr()), nb.value,
                                   ctypes.c_void_p(self.stream)), "wcc_batch_bind", h, True)
+
+    def rebind(self) -> None:
+        """Bind the same workspace again: every instance restarts at t = 0 with
+        an empty time-control ring (the states must be written again)."""
+        _check(load().wcc_batch_bind(self.h, ctypes.c_void_p(self.workspace.data_ptr()), self.workspace.numel(),
+                                     ctypes.c_void_p(self.stream)), "wcc_batch_bind", self.h, True)
 
     def ncells(self, b: int, parity: int) -> int:
         if self.bc == "periodic":

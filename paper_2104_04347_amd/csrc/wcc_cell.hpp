@@ -29,27 +29,38 @@ constexpr int ncomp() { return EQ == kEuler ? 3 : 1; }
 // ---------------------------------------------------------------------------
 // Exact rationals of the scheme, rounded once (constant-folded by the compiler).
 // ---------------------------------------------------------------------------
-constexpr double fac(int k) { return k <= 1 ? 1.0 : fac(k - 1) * (double)k; }
-constexpr double two_pow(int k) { return k <= 0 ? 1.0 : 2.0 * two_pow(k - 1); }
+// Non-recursive so that they inline into the unrolled loops and fold to
+// immediates (a recursive constexpr function called with a loop index is
+// compiled as a real call).
+__host__ __device__ constexpr double fac(int k) {
+  double f = 1.0;
+  for (int i = 2; i <= k; ++i) f *= (double)i;
+  return f;
+}
+__host__ __device__ constexpr double two_pow(int k) {
+  double p = 1.0;
+  for (int i = 0; i < k; ++i) p *= 2.0;
+  return p;
+}
 // 1/k!  (normalised Taylor coefficient)
-constexpr double inv_fac(int k) { return 1.0 / fac(k); }
+__host__ __device__ constexpr double inv_fac(int k) { return 1.0 / fac(k); }
 // weight of u_kx in the right half-cell average, Eq. SubEq:1DCellAVGR
-constexpr double half_avg(int k) { return 1.0 / (fac(k + 1) * two_pow(k)); }
+__host__ __device__ constexpr double half_avg(int k) { return 1.0 / (fac(k + 1) * two_pow(k)); }
 // weight of u_kx in the left half-cell average, Eq. SubEq:1DCellAVGL
-constexpr double half_avg_left(int k) { return (k % 2 == 0) ? half_avg(k) : -half_avg(k); }
+__host__ __device__ constexpr double half_avg_left(int k) { return (k % 2 == 0) ? half_avg(k) : -half_avg(k); }
 // minus the weight of u_kx in the cell average (Eq. SubEq:1DCellAVG -> Eq. 1DCalU)
-constexpr double neg_avg(int k) { return -half_avg(k); }
+__host__ __device__ constexpr double neg_avg(int k) { return -half_avg(k); }
 // minus the odd-moment weight of Eq. SubEq:Cal_1D_Derivatives_3
-constexpr double neg_odd(int m) { return (m % 2 == 1) ? -(2.0 / (fac(m) * two_pow(m))) : 0.0; }
+__host__ __device__ constexpr double neg_odd(int m) { return (m % 2 == 1) ? -(2.0 / (fac(m) * two_pow(m))) : 0.0; }
 // m!/(m+1)! of Eq. Cal1DFlux
-constexpr double flux_w(int m) { return 1.0 / (double)(m + 1); }
+__host__ __device__ constexpr double flux_w(int m) { return 1.0 / (double)(m + 1); }
 // (k+1)/m of the normalised CK identity
-constexpr double ck_ratio(int k, int m) { return (double)(k + 1) / (double)m; }
+__host__ __device__ constexpr double ck_ratio(int k, int m) { return (double)(k + 1) / (double)m; }
 // (+-1/2)^k/k!: the cell polynomial at the right / left edge
-constexpr double edge_plus(int k) { return 1.0 / (fac(k) * two_pow(k)); }
-constexpr double edge_minus(int k) { return (k % 2 == 0) ? edge_plus(k) : -edge_plus(k); }
+__host__ __device__ constexpr double edge_plus(int k) { return 1.0 / (fac(k) * two_pow(k)); }
+__host__ __device__ constexpr double edge_minus(int k) { return (k % 2 == 0) ? edge_plus(k) : -edge_plus(k); }
 // int_{-1/2}^{1/2} xi^s dxi for even s
-constexpr double even_moment(int s) { return 1.0 / ((double)(s + 1) * two_pow(s)); }
+__host__ __device__ constexpr double even_moment(int s) { return 1.0 / ((double)(s + 1) * two_pow(s)); }
 
 // fused multiply-add in the bulk type (v_fma_f64 / v_fma_f32)
 __device__ __forceinline__ double fmaT(double a, double b, double c) { return __builtin_fma(a, b, c); }

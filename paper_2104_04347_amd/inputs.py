@@ -161,12 +161,32 @@ def euler_taylor(data: EulerPiecewise, x: np.ndarray, dx: float, P: int) -> np.n
     q = np.empty((3, P + 1, x.size), dtype=np.float64)
     for k in range(P + 1):
         q[:, k, :] = dx ** k * data.conserved_deriv(x, k)
-    for j, xc in enumerate(x):
-        xa, xb = xc - 0.5 * dx, xc + 0.5 * dx
-        if data.jumps_in(xa, xb):
-            q[:, 0, j] = data.cell_mean(xa, xb)
-            q[:, 1:, j] = 0.0
+    for j in jump_cells(data, x, dx):
+        xa, xb = x[j] - 0.5 * dx, x[j] + 0.5 * dx
+        q[:, 0, j] = data.cell_mean(xa, xb)
+        q[:, 1:, j] = 0.0
     return q
+
+
+def jump_cells(data: EulerPiecewise, x: np.ndarray, dx: float) -> list:
+    """Indices of the cells (centres x, uniform spacing dx) whose open interval
+    contains a jump of the data, found from the few jump positions."""
+    if x.size == 0:
+        return []
+    cand = list(data.breaks)
+    if data.period is not None:
+        a, b0 = data.period
+        L = b0 - a
+        base = list(data.breaks) + ([a] if data.wrap_jump else [])
+        cand = [b + sh for b in base for sh in (-L, 0.0, L)]
+    out = set()
+    x0 = x[0] - 0.5 * dx
+    for b in cand:
+        j = int(np.floor((b - x0) / dx))
+        for jj in (j - 1, j, j + 1):
+            if 0 <= jj < x.size and x[jj] - 0.5 * dx < b < x[jj] + 0.5 * dx:
+                out.add(jj)
+    return sorted(out)
 
 
 def draw_state(rng: np.random.Generator):

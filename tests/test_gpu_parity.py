@@ -216,25 +216,33 @@ def test_determinism_repeat():
     assert np.array_equal(outs[1], outs[3])
 
 
+U32 = 2.0 ** -24   # binary32 unit round-off
+
+
 @pytest.mark.parametrize("P", [1, 2, 3, 4])
 def test_mixed_precision_smooth(P):
-    """FP32-mixed on smooth Euler data (entropy wave, limiter on): the point
-    values stay within 2e-6 (relative to the density scale) of the FP64
-    oracle after 400 half-steps; derivative DOFs within 2e-5 of their scale."""
-    N = 2000
+    """FP32-mixed on smooth Euler data (entropy wave, limiter on) against the
+    FP64 oracle after n = 400 half-steps.
+
+    Tolerance from the arithmetic: every half-step rounds the binary32 flux
+    integral and the binary32 vertex values once relative to the state scale S
+    (the scaled derivatives are differences of O(S) vertex values, so their
+    error is absolute in S, not relative to their own O(dx^k) size); the
+    rounding errors accumulate at most linearly, so every DOF must stay within
+    n * u32 * S and the mean point-value error within 4 sqrt(n) u32 S."""
+    N, n = 2000, 400
     q0, _ = inputs.euler_entropy_wave(P, N)
     kw = dict(x_left=0.0, x_right=2.0)
-    q, info, taken = gpu_run("euler", P, N, "periodic", q0, limiter=True, steps=400, cfl=0.25,
+    q, info, taken = gpu_run("euler", P, N, "periodic", q0, limiter=True, steps=n, cfl=0.25,
                              precision="fp32_mixed", **kw)
-    ref = oracle_run("euler", P, N, "periodic", q0, limiter=True, steps=400, cfl=0.25, **kw)
+    ref = oracle_run("euler", P, N, "periodic", q0, limiter=True, steps=n, cfl=0.25, **kw)
     assert taken == ref.half_steps and info.parity == ref.parity
-    assert abs(info.t - ref.t) <= 1e-6 * ref.t
+    assert abs(info.t - ref.t) <= n * U32 * ref.t
     for c in range(3):
-        scale = np.abs(ref.q[c, 0]).max()
-        assert np.abs(q[c, 0] - ref.q[c, 0]).max() <= 2e-6 * scale, c
-        for k in range(1, P + 1):
-            dscale = max(np.abs(ref.q[c, k]).max(), 1e-300)
-            assert np.abs(q[c, k] - ref.q[c, k]).max() <= 2e-5 * dscale + 1e-12 * scale, (c, k)
+        S = np.abs(ref.q[c, 0]).max()
+        err = np.abs(q[c] - ref.q[c])
+        assert err.max() <= n * U32 * S, (c, err.max() / S)
+        assert err[0].mean() <= 4 * np.sqrt(n) * U32 * S, (c, err[0].mean() / S)
 
 
 @pytest.mark.parametrize("P", [2, 3])
