@@ -120,6 +120,44 @@ def time_batch(args):
                 schedule=sched or "default")
 
 
+def time_large(args):
+    """Large 1D Euler: N = 16,777,216, P = 4, 8 seeded jumps with 9 states and
+    the density sine, periodic, CFL 0.20 per half-step, `large_steps`
+    half-steps in FP32-mixed and in binary64.  Reports throughput, the
+    conserved-total drift of the mixed run and its L1/Linf distance from the
+    binary64 run."""
+    import torch
+    from paper_2104_04347_amd import binding, inputs
+    N, P, cfl = args.large_N, 4, 0.20
+    q0, _ = inputs.euler_multi_jump(args.seed, P, N, n_jumps=8, bc="periodic")
+    out = {"config": f"1D Euler N={N}, P={P}, 8 jumps, periodic, CFL {cfl}, {args.large_steps} half-steps"}
+    finals = {}
+    for prec in ("fp32_mixed", "fp64"):
+        s = binding.Solver("euler", P, N, "periodic", limiter=True, precision=prec)
+        s.write(q0)
+        tot0 = s.totals()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.run(args.large_steps, cfl)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        tot = s.totals()
+        q, info = s.read()
+        finals[prec] = q[:, 0].copy()
+        abs0 = np.abs(q0[:, 0]).sum(axis=1) * (1.0 / N)   # scale of the totals
+        out[prec] = {"value": N * 3 * (P + 1) * args.large_steps / wall, "unit": "cell-DOF updates/s",
+                     "wall_s": wall, "ms_per_step": s.last_run_ms() / args.large_steps, "t": info.t,
+                     "flags": int(info.flags),
+                     "drift_rel": [float(abs(a - b) / c) for a, b, c in zip(tot, tot0, abs0)]}
+        del q
+        s.close()
+    d = finals["fp32_mixed"] - finals["fp64"]
+    scale = np.abs(finals["fp64"]).max(axis=1)
+    out["mixed_vs_fp64_point_values"] = {"L1_rel": [float(np.abs(d[c]).mean() / scale[c]) for c in range(3)],
+                                         "Linf_rel": [float(np.abs(d[c]).max() / scale[c]) for c in range(3)]}
+    return out
+
+
 def cpu_baseline(args, q0):
     """The FP64 oracle as it stands, single-threaded, on a bounded sample of
     the same workload: the first `cpu_steps` half-steps of the full mesh."""
@@ -160,7 +198,12 @@ def main():
     ap.add_argument("--batch-steps", type=int, default=100)
     ap.add_argument("--batch-warmup", type=int, default=24)
     ap.add_argument("--batch-schedule", default="", help="threads,blocks,mode for the batched kernels")
-    ap.add_argument("--cpu-steps", type=int, default=8)
+    ap.add_argument("--cpu-steps", type=int, default=24)
+    ap.add_argument("--large", action="store_true", help="also run the large 16.7M-cell P=4 workload")
+    ap.add_argument("--large-N", type=int, default=1 << 24)
+    ap.add_argument("--large-steps", type=int, default=10000)
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="also run 5 device-to-device copies of this many MiB (counter calibration)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -188,6 +231,21 @@ def main():
     if not args.no_batch:
         rb = time_batch(args)
         print(f"[bench] batched: {rb['value']:.1f} solves/s", file=sys.stderr, flush=True)
+
+    rl = None
+    if args.large:
+        rl = time_large(args)
+        print(f"[bench] large: mixed {rl['fp32_mixed']['value']:.3e} DOF/s, fp64 {rl['fp64']['value']:.3e} DOF/s",
+              file=sys.stderr, flush=True)
+
+    if args.calibrate_copy:
+        nbytes = args.calibrate_copy << 20
+        src = torch.ones(nbytes, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(f"[bench] copy calibration: 5 x {nbytes} bytes", file=sys.stderr, flush=True)
 
     counts = flop_counts()
     fl = counts[f"euler/P{args.P}/lim"]["flops"]
@@ -247,6 +305,8 @@ def main():
                               "gbs": round(rm["gbs"], 1), "tflops": round(rm["tflops"], 3)}
     if rb is not None:
         line["batched"] = rb
+    if rl is not None:
+        line["large"] = rl
     if not args.no_cpu:
         print("[bench] CPU baseline (oracle) ...", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(args, q0)

@@ -147,10 +147,12 @@ int wcc_read_dofs(wcc_ctx* ctx, double* host, int64_t cap, wcc_state_info* info)
  * Eq. SubEq:1DCellAVG), summed in cell order on the host.  Synchronous. */
 int wcc_totals(wcc_ctx* ctx, double* per_component);
 
-/* Launch shape of the half-step kernel: threads per block (multiple of 64,
- * <= 1024; 0 = default) and blocks (0 = enough to fill the device).  Used by
- * the autotuner; results do not depend on it. */
-int wcc_set_launch(wcc_ctx* ctx, int threads_per_block, int blocks);
+/* Launch shape of the half-step kernel: threads per block (64, 128, 192 or
+ * 256; 0 = 256), blocks (0 = enough to fill the device at the kernel's
+ * occupancy) and kernel variant (0: load a tile, then compute it; 1: load the
+ * next tile's inputs while computing the current one (default); -1 keeps the
+ * current variant).  Used by the autotuner; results do not depend on it. */
+int wcc_set_launch(wcc_ctx* ctx, int threads_per_block, int blocks, int variant);
 
 /* Number of kernel launches and the device time of the last wcc_run call
  * (HIP events around the enqueued work on the bound stream), in ms. */

@@ -51,25 +51,29 @@ def key_single(equation: str, P: int, N: int, precision: str, limiter: bool) -> 
     return f"single/{equation}/P{P}/{precision}/{'lim' if limiter else 'nolim'}/N2^{int(np.log2(max(N, 2)))}"
 
 
-def tune_single(solver: "binding.Solver", q0: np.ndarray, cfl: float, steps: int = 96,
-                threads=(64, 128, 256), block_factors=(0.5, 1, 2, 4, 8), verbose: bool = False) -> dict:
-    """Time the candidate shapes on `solver` (state q0, CFL cfl); keep the best."""
+def tune_single(solver: "binding.Solver", q0: np.ndarray, cfl: float, steps: int = 480,
+                threads=(64, 128, 256), block_factors=(0, 1, 2, 3, 4, 8), variants=(0, 1),
+                verbose: bool = False) -> dict:
+    """Time the candidate shapes on `solver` (state q0, CFL cfl); keep the best.
+    block factor 0 = the library's default (resident-block capacity)."""
     import torch
     cu = torch.cuda.get_device_properties(0).multi_processor_count
     results = []
-    for th in threads:
-        for bf in block_factors:
-            blocks = max(1, int(round(bf * cu)))
-            solver.set_launch(th, blocks)
-            solver.write(q0)
-            solver.run(48, cfl)            # warm-up, builds the graphs of this shape
-            torch.cuda.synchronize()
-            solver.run(steps, cfl)
-            ms = solver.last_run_ms()
-            results.append({"threads": th, "blocks": blocks, "ms_per_step": ms / steps})
-            if verbose:
-                print(f"  threads={th:4d} blocks={blocks:6d}: {ms / steps * 1e3:8.2f} us/half-step", flush=True)
-    solver.set_launch(0, 0)
+    for var in variants:
+        for th in threads:
+            for bf in block_factors:
+                blocks = 0 if bf == 0 else max(1, int(round(bf * cu)))
+                solver.set_launch(th, blocks, var)
+                solver.write(q0)
+                solver.run(48, cfl)            # warm-up, builds the graphs of this shape
+                torch.cuda.synchronize()
+                solver.run(steps, cfl)
+                ms = solver.last_run_ms()
+                results.append({"variant": var, "threads": th, "blocks": blocks, "ms_per_step": ms / steps})
+                if verbose:
+                    print(f"  variant={var} threads={th:4d} blocks={blocks:6d}: {ms / steps * 1e3:8.2f} us/half-step",
+                          flush=True)
+    solver.set_launch(0, 0, 0)
     solver.write(q0)
     solver.run(48, cfl)
     torch.cuda.synchronize()
@@ -77,14 +81,14 @@ def tune_single(solver: "binding.Solver", q0: np.ndarray, cfl: float, steps: int
     default_ms = solver.last_run_ms() / steps
     best = min(results, key=lambda r: r["ms_per_step"])
     if default_ms <= best["ms_per_step"]:
-        best = {"threads": 0, "blocks": 0, "ms_per_step": default_ms}
+        best = {"variant": 0, "threads": 0, "blocks": 0, "ms_per_step": default_ms}
     best["default_ms_per_step"] = default_ms
     best["tried"] = results
     c = _load_cache()
     c[key_single(solver.equation, solver.P, solver.N, binding.PRECISIONS_NAME[solver.params.precision],
-                 bool(solver.params.limiter))] = {k: best[k] for k in ("threads", "blocks", "ms_per_step")}
+                 bool(solver.params.limiter))] = {k: best[k] for k in ("variant", "threads", "blocks", "ms_per_step")}
     _save_cache(c)
-    solver.set_launch(best["threads"], best["blocks"])
+    solver.set_launch(best["threads"], best["blocks"], best["variant"])
     return best
 
 
@@ -95,14 +99,15 @@ def apply_single(solver: "binding.Solver") -> bool:
     c = _load_cache().get(k)
     if not c:
         return False
-    solver.set_launch(c["threads"], c["blocks"])
+    solver.set_launch(c["threads"], c["blocks"], c.get("variant", -1))
     return True
 
 
-def tune_batch(batch: "binding.Batch", states: list, cfl_by_P, steps: int = 24, modes=(1, 2),
+def tune_batch(batch: "binding.Batch", cfl_by_P, steps: int = 24, modes=(1, 2),
                threads=(128, 256), block_factors=(0, 1, 2, 4), verbose: bool = False) -> dict:
-    """Time batched schedules.  `states` are the instances' initial states; the
-    batch is rewritten before every candidate (a fresh bind restarts time)."""
+    """Time batched schedules on a batch whose instances are written and
+    prepared.  Candidates run consecutively from the evolving state (the cost
+    of a half-step does not depend on which half-step it is)."""
     import torch
     cu = torch.cuda.get_device_properties(0).multi_processor_count
     results = []
@@ -111,19 +116,11 @@ def tune_batch(batch: "binding.Batch", states: list, cfl_by_P, steps: int = 24, 
             for bf in block_factors:
                 blocks = 0 if bf == 0 else max(1, int(round(bf * cu)))
                 batch.set_schedule(th, blocks, mode)
-                batch.rebind()
-                for b, q in enumerate(states):
-                    batch.write(b, q)
-                batch.prepare()
-                batch.run(steps, cfl_by_P)          # warm-up, builds graphs
+                batch.run(steps, cfl_by_P)          # warm-up, builds the graphs of this schedule
                 torch.cuda.synchronize()
-                t0 = time.perf_counter()
                 batch.run(steps, cfl_by_P)
-                torch.cuda.synchronize()
-                wall = time.perf_counter() - t0
                 ms = batch.last_run_ms()
-                results.append({"mode": mode, "threads": th, "blocks": blocks, "ms_per_step": ms / steps,
-                                "wall_ms_per_step": wall * 1e3 / steps})
+                results.append({"mode": mode, "threads": th, "blocks": blocks, "ms_per_step": ms / steps})
                 if verbose:
                     print(f"  mode={mode} threads={th} blocks={blocks}: {ms / steps:.3f} ms/half-step", flush=True)
     best = min(results, key=lambda r: r["ms_per_step"])

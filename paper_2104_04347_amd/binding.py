@@ -61,7 +61,7 @@ SIGNATURES = {
     "wcc_advance": ([_vp, _c.c_double, _c.c_double, _i64, _c.POINTER(_i64)], _c.c_int),
     "wcc_read_dofs": ([_vp, _dp, _i64, _c.POINTER(wcc_state_info)], _c.c_int),
     "wcc_totals": ([_vp, _dp], _c.c_int),
-    "wcc_set_launch": ([_vp, _c.c_int, _c.c_int], _c.c_int),
+    "wcc_set_launch": ([_vp, _c.c_int, _c.c_int, _c.c_int], _c.c_int),
     "wcc_last_run_ms": ([_vp, _dp], _c.c_int),
     "wcc_strerror": ([_c.c_int], _c.c_char_p),
     "wcc_last_error": ([_vp], _c.c_char_p),
@@ -207,8 +207,8 @@ class Solver:
         _check(load().wcc_totals(self.h, _dptr(out)), "wcc_totals", self.h)
         return out
 
-    def set_launch(self, threads: int = 0, blocks: int = 0) -> None:
-        _check(load().wcc_set_launch(self.h, int(threads), int(blocks)), "wcc_set_launch", self.h)
+    def set_launch(self, threads: int = 0, blocks: int = 0, variant: int = -1) -> None:
+        _check(load().wcc_set_launch(self.h, int(threads), int(blocks), int(variant)), "wcc_set_launch", self.h)
 
     def last_run_ms(self) -> float:
         ms = ctypes.c_double()

@@ -18,7 +18,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/wcc.h"
+#include "wcc.h"
 #include "wcc_internal.hpp"
 
 using wcc::Ctrl;
@@ -55,6 +55,7 @@ struct wcc_ctx {
   int64_t launched = 0;     // kernels enqueued since the write (slot = launched % 3)
   int64_t steps = 0;        // half-steps known to be done (exact after a sync)
   int threads = 256, blocks = 0;
+  int prefetch = 0;          // kernel variant: 1 = prefetch the next tile's inputs
   int cu = 0;
   hipStream_t capture = nullptr;
   hipGraphExec_t graphs[6] = {};
@@ -128,8 +129,10 @@ int blocks_for(wcc_ctx* c) {
   const int waves = c->threads / 64;
   int per_cu = 0;
   hipError_t e = c->prm.precision == WCC_FP64
-                     ? wcc::occupancy_half_step<double>(c->eq, c->P, c->prm.limiter != 0, c->threads, &per_cu)
-                     : wcc::occupancy_half_step<float>(c->eq, c->P, c->prm.limiter != 0, c->threads, &per_cu);
+                     ? wcc::occupancy_half_step<double>(c->eq, c->P, c->prm.limiter != 0, c->prefetch, c->threads,
+                                                        &per_cu)
+                     : wcc::occupancy_half_step<float>(c->eq, c->P, c->prm.limiter != 0, c->prefetch, c->threads,
+                                                       &per_cu);
   if (e != hipSuccess || per_cu < 1) per_cu = 1;
   int64_t full = (int64_t)per_cu * c->cu;
   int64_t need = (tiles + waves - 1) / waves;
@@ -142,10 +145,10 @@ int enqueue_step(wcc_ctx* c, int parity, int slot, double dt_fixed, hipStream_t 
   hipError_t e;
   if (c->prm.precision == WCC_FP64)
     e = wcc::launch_half_step<double>(args_for<double>(c, parity, slot, dt_fixed), c->eq, c->P, c->prm.limiter != 0,
-                                      blocks, c->threads, s);
+                                      c->prefetch, blocks, c->threads, s);
   else
     e = wcc::launch_half_step<float>(args_for<float>(c, parity, slot, dt_fixed), c->eq, c->P, c->prm.limiter != 0,
-                                     blocks, c->threads, s);
+                                     c->prefetch, blocks, c->threads, s);
   if (e != hipSuccess) return fail(c, WCC_EDEVICE, "half-step launch: %s", hipGetErrorString(e));
   return WCC_OK;
 }
@@ -222,7 +225,8 @@ int wcc_create(int equation, int P, int64_t N, int bc, const wcc_params* params,
   if (!(prm.x_right > prm.x_left) || !(prm.eps >= 0.0)) return WCC_EINVAL;
   if (prm.precision != WCC_FP64 && prm.precision != WCC_FP32_MIXED) return WCC_EINVAL;
   if (equation == WCC_EULER && !(prm.gamma > 1.0)) return WCC_EINVAL;
-  if (N > ((int64_t)1 << 40)) return WCC_EINVAL;
+  // rows are addressed with 32-bit byte offsets: ld * 8 bytes < 4 GiB
+  if (N > ((int64_t)1 << 28)) return WCC_EINVAL;
   wcc_ctx* c = new wcc_ctx();
   c->eq = equation;
   c->P = P;
@@ -534,8 +538,10 @@ int wcc_totals(wcc_ctx* c, double* per_component) {
   return WCC_OK;
 }
 
-int wcc_set_launch(wcc_ctx* c, int threads_per_block, int blocks) {
+int wcc_set_launch(wcc_ctx* c, int threads_per_block, int blocks, int variant) {
   if (!c) return WCC_EINVAL;
+  if (variant < -1 || variant > 1) return fail(c, WCC_EINVAL, "variant must be -1 (keep), 0 or 1");
+  if (variant >= 0) c->prefetch = variant;
   if (threads_per_block != 0 && (threads_per_block % 64 != 0 || threads_per_block < 64 || threads_per_block > 256))
     return fail(c, WCC_EINVAL, "threads per block must be 64, 128, 192 or 256");
   if (blocks < 0) return fail(c, WCC_EINVAL, "negative block count");

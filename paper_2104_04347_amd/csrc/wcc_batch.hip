@@ -24,7 +24,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/wcc.h"
+#include "wcc.h"
 #include "wcc_cell.hpp"
 #include "wcc_internal.hpp"
 #include "wcc_tile.hpp"
@@ -408,7 +408,7 @@ int wcc_batch_create(int equation, int B, const int32_t* P, const int64_t* N, in
     return WCC_EINVAL;
   if (equation == WCC_EULER && !(prm.gamma > 1.0)) return WCC_EINVAL;
   for (int i = 0; i < B; ++i)
-    if (P[i] < 0 || P[i] > wcc::kBatchPMax || N[i] < 2 || N[i] > (1LL << 31)) return WCC_EINVAL;
+    if (P[i] < 0 || P[i] > wcc::kBatchPMax || N[i] < 2 || N[i] > (1LL << 28)) return WCC_EINVAL;
   wcc_batch* b = new wcc_batch();
   b->eq = equation;
   b->bc = bc;

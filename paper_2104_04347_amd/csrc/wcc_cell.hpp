@@ -68,8 +68,21 @@ __device__ __forceinline__ float fmaT(float a, float b, float c) { return __buil
 __device__ __forceinline__ double absT(double a) { return __builtin_fabs(a); }
 __device__ __forceinline__ float absT(float a) { return __builtin_fabsf(a); }
 __device__ __forceinline__ double sqrtT(double a) { return __builtin_sqrt(a); }
-__device__ __forceinline__ float sqrtT(float a) { return __builtin_sqrtf(a); }
+__device__ __forceinline__ float sqrtT(float a) { return __builtin_amdgcn_sqrtf(a); }
 __device__ __forceinline__ bool finiteT(double a) { return __builtin_isfinite(a); }
+
+// Division in the bulk type.  binary64: the IEEE quotient (the binary64 mode
+// is bit-reproducible).  binary32 (FP32-mixed mode, checked against the FP64
+// oracle with a tolerance): the hardware reciprocal (1 ulp) times the
+// numerator, both scaled by 2^100 when the divisor is below 2^-100 so that
+// subnormal divisors (the limiter's epsilon is a binary32 subnormal) do not
+// overflow the reciprocal; the scaling by a power of two is exact.
+__device__ __forceinline__ double divT(double a, double b) { return a / b; }
+__device__ __forceinline__ float divT(float a, float b) {
+  const bool tiny = __builtin_fabsf(b) < 0x1p-100f;
+  const float s = tiny ? 0x1p100f : 1.0f;
+  return (a * s) * __builtin_amdgcn_rcpf(b * s);
+}
 __device__ __forceinline__ bool finiteT(float a) { return __builtin_isfinite(a); }
 
 // Physical parameters in the bulk type.
@@ -167,7 +180,7 @@ __device__ __forceinline__ void old_cell(const double (&p)[ncomp<EQ>()], const R
       } else if constexpr (EQ == kBurgers) {
         G[0].v[k][j] = (R)0.5 * tri_mul<P>(T[0], T[0], k, j);
       } else {
-        if (k == 0 && j == 0) rinv = (R)1.0 / T[0].v[0][0];
+        if (k == 0 && j == 0) rinv = divT((R)1.0, T[0].v[0][0]);
         vel.v[k][j] = tri_div<P>(T[1], T[0], vel, rinv, k, j);
         const R kin = tri_mul<P>(T[1], vel, k, j);                     // rho u^2
         const R pre = ph.gm1 * (T[2].v[k][j] - (R)0.5 * kin);           // p
@@ -276,7 +289,7 @@ __device__ __forceinline__ void limiter_weights(float b0, float b1, float b2, fl
     // w_m = (1/q_m)^2 / sum_l (1/q_l)^2 = (qmin/q_m)^2 / sum_l (qmin/q_l)^2
     const float q0 = b0 + eps, q1 = b1 + eps, q2 = b2 + eps;
     const float qm = __builtin_fminf(q0, __builtin_fminf(q1, q2));
-    const float x0 = qm / q0, x1 = qm / q1, x2 = qm / q2;
+    const float x0 = divT(qm, q0), x1 = divT(qm, q1), x2 = divT(qm, q2);
     wh0 = x0 * x0;
     wh1 = x1 * x1;
     wh2 = x2 * x2;
@@ -287,18 +300,18 @@ __device__ __forceinline__ void limiter_weights(float b0, float b1, float b2, fl
                 q2 = __builtin_fmaf(b2, b2, eps);
     const float qm = __builtin_fminf(q0, __builtin_fminf(q1, q2));
     if (st >= qm) {
-      const float g = qm / st, x0 = qm / q0, x1 = qm / q1, x2 = qm / q2;
+      const float g = divT(qm, st), x0 = divT(qm, q0), x1 = divT(qm, q1), x2 = divT(qm, q2);
       wh0 = __builtin_fmaf(x0, x0, g * g);
       wh1 = x1 * x1;
       wh2 = x2 * x2;
     } else {
-      const float r0 = st / q0, r1 = st / q1, r2 = st / q2;
+      const float r0 = divT(st, q0), r1 = divT(st, q1), r2 = divT(st, q2);
       wh0 = __builtin_fmaf(r0, r0, 1.0f);
       wh1 = r1 * r1;
       wh2 = r2 * r2;
     }
   }
-  const float inv = 1.0f / ((wh0 + wh1) + wh2);
+  const float inv = divT(1.0f, (wh0 + wh1) + wh2);
   w0 = wh0 * inv;
   w1 = wh1 * inv;
   w2 = wh2 * inv;
@@ -345,9 +358,9 @@ __device__ __forceinline__ void limit_field(R (&d)[P + 1], R abar, R vl, R vr, R
 // Velocity, pressure and sound speed of a conserved Euler state.
 template <class R>
 __device__ __forceinline__ void euler_uc(const Phys<R>& ph, R rho, R mom, R ene, R& u, R& p, R& c) {
-  u = mom / rho;
+  u = divT(mom, rho);
   p = ph.gm1 * (ene - (R)0.5 * mom * u);
-  c = sqrtT((ph.gamma * p) / rho);
+  c = sqrtT(divT(ph.gamma * p, rho));
 }
 
 template <class R>
@@ -409,8 +422,8 @@ __device__ __forceinline__ int new_cell(const OldOut<EQ, P, R>& L, const double 
       // the two vertex values and the derivatives; the limited field is added
       // into R*cd column by column (the same order as a full 3x3 product).
       const R rho = (R)abar[0];
-      const R H = ((R)abar[2] + ep) / rho;
-      const R ic = (R)1.0 / ec;
+      const R H = divT((R)abar[2] + ep, rho);
+      const R ic = divT((R)1.0, ec);
       const R b1 = ph.gm1 * (ic * ic);
       const R b2 = (R)0.5 * b1 * (eu * eu);
       const R uic = eu * ic, b1u = b1 * eu;

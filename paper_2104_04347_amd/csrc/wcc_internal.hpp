@@ -81,10 +81,11 @@ struct BatchArgs {
 };
 
 template <class R>
-hipError_t launch_half_step(const StepArgs<R>& a, int eq, int P, bool lim, int blocks, int threads, hipStream_t s);
+hipError_t launch_half_step(const StepArgs<R>& a, int eq, int P, bool lim, int prefetch, int blocks, int threads,
+                            hipStream_t s);
 template <class R>
 hipError_t launch_state_speed(const StepArgs<R>& a, int eq, int P, int blocks, hipStream_t s);
 template <class R>
-hipError_t occupancy_half_step(int eq, int P, bool lim, int threads, int* blocks_per_cu);
+hipError_t occupancy_half_step(int eq, int P, bool lim, int prefetch, int threads, int* blocks_per_cu);
 
 }  // namespace wcc

@@ -26,7 +26,10 @@
 
 namespace wcc {
 
-template <int EQ, int P, bool LIM, class R>
+// PF = 1: each wave loads the inputs of its next tile before expanding the
+// current one, so every wave keeps one tile of loads in flight while it
+// computes (costs the registers of one tile's inputs).
+template <int EQ, int P, bool LIM, class R, int PF>
 __global__ __launch_bounds__(256) void k_half_step(const StepArgs<R> a) {
   double dt;
   if (!step_time(a.ctrl, a.slot, a.dx, a.dt_fixed, blockIdx.x == 0 && threadIdx.x == 0, dt)) return;
@@ -39,8 +42,24 @@ __global__ __launch_bounds__(256) void k_half_step(const StepArgs<R> a) {
   const int64_t t_stop = t_begin + per_block < tiles ? t_begin + per_block : tiles;
   double smax = 0.0;
   unsigned flags = 0u;
-  for (int64_t tile = t_begin + wave; tile < t_stop; tile += nw)
-    run_tile<EQ, P, LIM, R>(a, tile, lam, nlam, lane, smax, flags);
+  if constexpr (PF == 0) {
+    for (int64_t tile = t_begin + wave; tile < t_stop; tile += nw)
+      run_tile<EQ, P, LIM, R>(a, tile, lam, nlam, lane, smax, flags);
+  } else {
+    int64_t tile = t_begin + wave;
+    if (tile < t_stop) {
+      TileIn<EQ, P, R> cur;
+      fetch_tile<EQ, P, R>(a, tile, lane, cur);
+      for (; tile < t_stop; tile += nw) {
+        TileIn<EQ, P, R> nxt;
+        const int64_t t2 = tile + nw < t_stop ? tile + nw : tile;   // in bounds; unused at the end
+        fetch_tile<EQ, P, R>(a, t2, lane, nxt);
+        __builtin_amdgcn_sched_barrier(0);
+        compute_tile<EQ, P, LIM, R>(a, tile, cur, lam, nlam, lane, smax, flags);
+        cur = nxt;
+      }
+    }
+  }
   publish(a.ctrl, a.slot, smax, flags);
 }
 
@@ -74,35 +93,39 @@ __global__ __launch_bounds__(256) void k_state_speed(const StepArgs<R> a) {
 // Host-side dispatch over the compile-time variants.
 // ---------------------------------------------------------------------------
 template <int EQ, int P, bool LIM, class R>
-static hipError_t launch_one(const StepArgs<R>& a, int blocks, int threads, hipStream_t s) {
-  hipLaunchKernelGGL((k_half_step<EQ, P, LIM, R>), dim3(blocks), dim3(threads), 0, s, a);
+static hipError_t launch_one(const StepArgs<R>& a, int pf, int blocks, int threads, hipStream_t s) {
+  if (pf)
+    hipLaunchKernelGGL((k_half_step<EQ, P, LIM, R, 1>), dim3(blocks), dim3(threads), 0, s, a);
+  else
+    hipLaunchKernelGGL((k_half_step<EQ, P, LIM, R, 0>), dim3(blocks), dim3(threads), 0, s, a);
   return hipGetLastError();
 }
 
 template <int EQ, int P, class R>
-static hipError_t launch_lim(const StepArgs<R>& a, bool lim, int blocks, int threads, hipStream_t s) {
-  if (lim && P >= 1) return launch_one<EQ, P, true, R>(a, blocks, threads, s);
-  return launch_one<EQ, P, false, R>(a, blocks, threads, s);
+static hipError_t launch_lim(const StepArgs<R>& a, bool lim, int pf, int blocks, int threads, hipStream_t s) {
+  if (lim && P >= 1) return launch_one<EQ, P, true, R>(a, pf, blocks, threads, s);
+  return launch_one<EQ, P, false, R>(a, pf, blocks, threads, s);
 }
 
 template <int EQ, class R>
-static hipError_t launch_p(const StepArgs<R>& a, int P, bool lim, int blocks, int threads, hipStream_t s) {
+static hipError_t launch_p(const StepArgs<R>& a, int P, bool lim, int pf, int blocks, int threads, hipStream_t s) {
   switch (P) {
-    case 0: return launch_lim<EQ, 0, R>(a, false, blocks, threads, s);
-    case 1: return launch_lim<EQ, 1, R>(a, lim, blocks, threads, s);
-    case 2: return launch_lim<EQ, 2, R>(a, lim, blocks, threads, s);
-    case 3: return launch_lim<EQ, 3, R>(a, lim, blocks, threads, s);
-    case 4: return launch_lim<EQ, 4, R>(a, lim, blocks, threads, s);
+    case 0: return launch_lim<EQ, 0, R>(a, false, pf, blocks, threads, s);
+    case 1: return launch_lim<EQ, 1, R>(a, lim, pf, blocks, threads, s);
+    case 2: return launch_lim<EQ, 2, R>(a, lim, pf, blocks, threads, s);
+    case 3: return launch_lim<EQ, 3, R>(a, lim, pf, blocks, threads, s);
+    case 4: return launch_lim<EQ, 4, R>(a, lim, pf, blocks, threads, s);
   }
   return hipErrorInvalidValue;
 }
 
 template <class R>
-hipError_t launch_half_step(const StepArgs<R>& a, int eq, int P, bool lim, int blocks, int threads, hipStream_t s) {
+hipError_t launch_half_step(const StepArgs<R>& a, int eq, int P, bool lim, int pf, int blocks, int threads,
+                            hipStream_t s) {
   switch (eq) {
-    case kAdvection: return launch_p<kAdvection, R>(a, P, lim, blocks, threads, s);
-    case kBurgers: return launch_p<kBurgers, R>(a, P, lim, blocks, threads, s);
-    case kEuler: return launch_p<kEuler, R>(a, P, lim, blocks, threads, s);
+    case kAdvection: return launch_p<kAdvection, R>(a, P, lim, pf, blocks, threads, s);
+    case kBurgers: return launch_p<kBurgers, R>(a, P, lim, pf, blocks, threads, s);
+    case kEuler: return launch_p<kEuler, R>(a, P, lim, pf, blocks, threads, s);
   }
   return hipErrorInvalidValue;
 }
@@ -131,11 +154,12 @@ hipError_t launch_state_speed(const StepArgs<R>& a, int eq, int P, int blocks, h
 }
 
 template <class R>
-hipError_t occupancy_half_step(int eq, int P, bool lim, int threads, int* blocks_per_cu) {
+hipError_t occupancy_half_step(int eq, int P, bool lim, int pf, int threads, int* blocks_per_cu) {
   // Queried for the heaviest variant that can run; the kernel is the same for
   // every equation except in register use, so ask for the exact one.
   const void* f = nullptr;
-#define WCC_K(E, PP, L) reinterpret_cast<const void*>(&k_half_step<E, PP, L, R>)
+#define WCC_K(E, PP, L) (pf ? reinterpret_cast<const void*>(&k_half_step<E, PP, L, R, 1>) \
+                            : reinterpret_cast<const void*>(&k_half_step<E, PP, L, R, 0>))
 #define WCC_PSWITCH(E)                                                            \
   switch (P) {                                                                    \
     case 0: f = WCC_K(E, 0, false); break;                                        \
@@ -153,11 +177,11 @@ hipError_t occupancy_half_step(int eq, int P, bool lim, int threads, int* blocks
   return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, f, threads, 0);
 }
 
-template hipError_t launch_half_step<double>(const StepArgs<double>&, int, int, bool, int, int, hipStream_t);
-template hipError_t launch_half_step<float>(const StepArgs<float>&, int, int, bool, int, int, hipStream_t);
+template hipError_t launch_half_step<double>(const StepArgs<double>&, int, int, bool, int, int, int, hipStream_t);
+template hipError_t launch_half_step<float>(const StepArgs<float>&, int, int, bool, int, int, int, hipStream_t);
 template hipError_t launch_state_speed<double>(const StepArgs<double>&, int, int, int, hipStream_t);
 template hipError_t launch_state_speed<float>(const StepArgs<float>&, int, int, int, hipStream_t);
-template hipError_t occupancy_half_step<double>(int, int, bool, int, int*);
-template hipError_t occupancy_half_step<float>(int, int, bool, int, int*);
+template hipError_t occupancy_half_step<double>(int, int, bool, int, int, int*);
+template hipError_t occupancy_half_step<float>(int, int, bool, int, int, int*);
 
 }  // namespace wcc

@@ -103,6 +103,17 @@ __device__ __forceinline__ void publish(Ctrl* ctrl, int slot, double smax, unsig
   }
 }
 
+// Element i of a row: uniform base pointer plus a 32-bit byte offset, the
+// form the global load/store instructions take with an SGPR base.
+template <class T>
+__device__ __forceinline__ T row_at(const T* base, uint32_t i) {
+  return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + (uint32_t)(i * (uint32_t)sizeof(T)));
+}
+template <class T>
+__device__ __forceinline__ void row_store(T* base, uint32_t i, T v) {
+  *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + (uint32_t)(i * (uint32_t)sizeof(T))) = v;
+}
+
 // Load the old cell `o` (already mapped into [0, n_old)), or a Dirichlet ghost.
 template <int EQ, int P, class R>
 __device__ __forceinline__ void load_cell(const double* __restrict__ pv, const R* __restrict__ dv, int64_t ld,
@@ -134,8 +145,11 @@ __device__ __forceinline__ int64_t map_old(int64_t o, int64_t n_old, int64_t N, 
                                            int& ghost) {
   ghost = 0;
   if (bc == kPeriodic) {
-    o %= N;
+    // a tile reaches at most one cell before 0 and 63 past the end, so one
+    // wrap suffices unless N < 64 (then fall back to the remainder)
     if (o < 0) o += N;
+    else if (o >= N) o -= N;
+    if (o >= N) o %= N;
     return o;
   }
   if (o < 0) {
@@ -149,20 +163,47 @@ __device__ __forceinline__ int64_t map_old(int64_t o, int64_t n_old, int64_t N, 
   return o;
 }
 
-template <int EQ, int P, bool LIM, class R>
-__device__ __forceinline__ void run_tile(const StepArgs<R>& a, int64_t tile, double lam, R nlam, int lane,
-                                         double& smax, unsigned& flags) {
+// The old-cell inputs of one lane for one tile (loaded ahead of use when the
+// kernel prefetches the next tile while computing the current one).
+template <int EQ, int P, class R>
+struct TileIn {
+  double p[ncomp<EQ>()];
+  R d[ncomp<EQ>()][P + 1];
+};
+
+template <int EQ, int P, class R>
+__device__ __forceinline__ void fetch_tile(const StepArgs<R>& a, int64_t tile, int lane, TileIn<EQ, P, R>& in) {
   constexpr int NC = ncomp<EQ>();
-  constexpr int PV = P > 0 ? P : 1;
   const int64_t j0 = tile * 63;
   int ghost;
   const int64_t o = map_old(j0 + lane - (a.parity_old == 1 ? 1 : 0), a.n_old, a.N, a.bc, a.parity_old, ghost);
-  double p[NC];
-  R d[NC][P + 1];
-  load_cell<EQ, P, R>(a.p_old, a.d_old, a.ld, o, ghost, a, p, d);
+  // rows addressed by a uniform 64-bit base and a 32-bit byte offset (rows
+  // are shorter than 4 GiB, checked at creation)
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    in.p[c] = row_at(a.p_old + c * a.ld, (uint32_t)o);
+    in.d[c][0] = (R)0;
+#pragma unroll
+    for (int k = 1; k <= P; ++k) in.d[c][k] = row_at(a.d_old + (c * P + (k - 1)) * a.ld, (uint32_t)o);
+  }
+  if (ghost) {
+    const double* g = a.ctrl->ghost[ghost - 1];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      in.p[c] = g[c];
+#pragma unroll
+      for (int k = 1; k <= P; ++k) in.d[c][k] = (R)0;
+    }
+  }
+}
 
+template <int EQ, int P, bool LIM, class R>
+__device__ __forceinline__ void compute_tile(const StepArgs<R>& a, int64_t tile, const TileIn<EQ, P, R>& in,
+                                             double lam, R nlam, int lane, double& smax, unsigned& flags) {
+  constexpr int NC = ncomp<EQ>();
+  constexpr int PV = P > 0 ? P : 1;
   OldOut<EQ, P, R> X;
-  old_cell<EQ, P, R>(p, d, nlam, a.ph, X);
+  old_cell<EQ, P, R>(in.p, in.d, nlam, a.ph, X);
   __builtin_amdgcn_sched_barrier(0);
 
   // Right parent's half of the interface data from lane + 1.
@@ -178,7 +219,7 @@ __device__ __forceinline__ void run_tile(const StepArgs<R>& a, int64_t tile, dou
     if (P == 0) V_R[c][0] = (R)0;
   }
 
-  const int64_t j = j0 + lane;
+  const int64_t j = tile * 63 + lane;
   if (lane < 63 && j < a.n_new) {
     double pn[NC];
     R dn[NC][P + 1];
@@ -188,11 +229,19 @@ __device__ __forceinline__ void run_tile(const StepArgs<R>& a, int64_t tile, dou
     if (!(sp == sp)) smax = sp;
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
-      a.p_new[c * a.ld + j] = pn[c];
+      row_store(a.p_new + c * a.ld, (uint32_t)j, pn[c]);
 #pragma unroll
-      for (int k = 1; k <= P; ++k) a.d_new[(c * P + (k - 1)) * a.ld + j] = dn[c][k];
+      for (int k = 1; k <= P; ++k) row_store(a.d_new + (c * P + (k - 1)) * a.ld, (uint32_t)j, dn[c][k]);
     }
   }
+}
+
+template <int EQ, int P, bool LIM, class R>
+__device__ __forceinline__ void run_tile(const StepArgs<R>& a, int64_t tile, double lam, R nlam, int lane,
+                                         double& smax, unsigned& flags) {
+  TileIn<EQ, P, R> in;
+  fetch_tile<EQ, P, R>(a, tile, lane, in);
+  compute_tile<EQ, P, LIM, R>(a, tile, in, lam, nlam, lane, smax, flags);
 }
 
 }  // namespace wcc
