@@ -34,6 +34,35 @@ FP32_VALU_PEAK = 157.3e12  # flop/s (packed / dual-issue)
 CFL_BY_P = [0.4, 0.4, 0.3, 0.25, 0.25]
 
 
+def kernel_source_hash() -> str:
+    """SHA-256 over the HIP sources and headers of the kernels (traffic figures
+    measured with counters are only reported for the kernel they were taken on)."""
+    import hashlib
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_2104_04347_amd", "csrc")
+    for name in sorted(os.listdir(d)):
+        if name.endswith((".hip", ".hpp")):
+            with open(os.path.join(d, name), "rb") as f:
+                h.update(name.encode() + b"\0" + f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel: str, N: int):
+    """HBM bytes per launch from the committed counter record (FETCH_SIZE and
+    WRITE_SIZE, scaled by the copy-kernel calibration), or None when the
+    record is for another kernel build or size."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        with open(path) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    e = rec.get(kernel)
+    if not e or e.get("source_sha256") != kernel_source_hash() or e.get("N") != N:
+        return None
+    return e["fetch_bytes"] + e["write_bytes"]
+
+
 def flop_counts():
     with open(os.path.join(ROOT, "paper_2104_04347_amd", "flop_counts.json")) as f:
         return json.load(f)["counts"]
@@ -268,7 +297,7 @@ def main():
         "peak": HBM_PEAK / 1e9 if bound_hbm else FP64_VALU_PEAK / 1e12,
         "unit": "GB/s" if bound_hbm else "TFLOP/s",
         "frac": round(ro["hbm_frac"] if bound_hbm else ro["alu_frac"], 4),
-        "traffic": None,
+        "traffic": measured_traffic(f"k_half_step<euler,P={args.P},limiter,f64>", args.N),
         "kernel": f"k_half_step<euler,P={args.P},limiter,f64>",
         "launch_us": round(ro["launch_us"], 2),
         "bytes_per_launch": ro["bytes_per_launch"],

@@ -5,7 +5,8 @@
 // graphs.  Device memory and the stream come from the caller (wcc_bind).
 //
 // Workspace layout (all offsets 256-byte aligned):
-//   [ctrl: Ctrl]  [p0: nc*ld doubles]  [p1]  [d0: nc*P*ld R]  [d1]
+//   [ctrl: Ctrl] [parts: 3 x 64 partial wave-speed maxima, 64 B apart]
+//   [p0: nc*ld doubles]  [p1]  [d0: nc*P*ld R]  [d1]
 // with ld = max cells per mesh rounded up to 64.  Buffer b holds the state
 // of mesh parity b; a half-step reads buffer `parity` and writes the other.
 #include <hip/hip_runtime.h>
@@ -47,6 +48,7 @@ struct wcc_ctx {
   size_t ws_bytes = 0;
   hipStream_t stream = nullptr;
   Ctrl* ctrl = nullptr;
+  unsigned long long* parts = nullptr;
   double* p[2] = {nullptr, nullptr};
   void* d[2] = {nullptr, nullptr};
   // host-side view of the march
@@ -63,6 +65,7 @@ struct wcc_ctx {
   double last_run_ms = 0.0;
   std::string err;
   std::vector<float> stage;
+  std::vector<unsigned long long> stage_zero;
 };
 
 namespace {
@@ -119,6 +122,7 @@ StepArgs<R> args_for(const wcc_ctx* c, int parity, int slot, double dt_fixed) {
   a.dt_fixed = dt_fixed;
   a.ph = phys_of<R>(c);
   a.ctrl = c->ctrl;
+  a.parts = c->parts;
   a.slot = slot;
   return a;
 }
@@ -189,9 +193,19 @@ int set_ctrl_fields(wcc_ctx* c, double t_end, double cfl) {
   return WCC_OK;
 }
 
+// Read the control block (synchronising the stream); smax[slot] of the copy
+// is replaced by the max of the slot's partial entries.
 int read_ctrl(wcc_ctx* c, Ctrl* h) {
+  static_assert(wcc::kSmaxPartsBytes % 256 == 0, "parts region size");
+  std::vector<unsigned long long> parts(wcc::kSmaxPartsBytes / sizeof(unsigned long long));
   HIPCHK(c, hipMemcpyAsync(h, c->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipMemcpyAsync(parts.data(), c->parts, wcc::kSmaxPartsBytes, hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
+  for (int s = 0; s < 3; ++s) {
+    unsigned long long m = 0;
+    for (int i = 0; i < wcc::kSmaxParts; ++i) m = std::max(m, parts[(size_t)(s * wcc::kSmaxParts + i) * wcc::kSmaxStride]);
+    h->smax[s] = m;
+  }
   c->steps = h->steps_done;
   return WCC_OK;
 }
@@ -251,7 +265,7 @@ int wcc_workspace_bytes(const wcc_ctx* c, size_t* bytes) {
   if (!c || !bytes) return WCC_EINVAL;
   const size_t pb = align256((size_t)c->nc * (size_t)c->ld * 8);
   const size_t db = align256((size_t)c->nc * (size_t)c->P * (size_t)c->ld * c->elem);
-  *bytes = align256(sizeof(Ctrl)) + 2 * pb + 2 * db;
+  *bytes = align256(sizeof(Ctrl)) + wcc::kSmaxPartsBytes + 2 * pb + 2 * db;
   return WCC_OK;
 }
 
@@ -271,6 +285,8 @@ int wcc_bind(wcc_ctx* c, void* dev_ptr, size_t bytes, void* hip_stream) {
   char* q = c->ws;
   c->ctrl = reinterpret_cast<Ctrl*>(q);
   q += align256(sizeof(Ctrl));
+  c->parts = reinterpret_cast<unsigned long long*>(q);
+  q += wcc::kSmaxPartsBytes;
   c->p[0] = reinterpret_cast<double*>(q);
   q += pb;
   c->p[1] = reinterpret_cast<double*>(q);
@@ -327,6 +343,8 @@ int wcc_write_dofs(wcc_ctx* c, const double* host, int64_t n_cells, int parity, 
     h.ghost[1][i] = c->prm.right_state[i];
   }
   HIPCHK(c, hipMemcpyAsync(c->ctrl, &h, sizeof h, hipMemcpyHostToDevice, c->stream));
+  c->stage_zero.assign(wcc::kSmaxPartsBytes / sizeof(unsigned long long), 0ull);
+  HIPCHK(c, hipMemcpyAsync(c->parts, c->stage_zero.data(), wcc::kSmaxPartsBytes, hipMemcpyHostToDevice, c->stream));
   // wave speed of the written state into slot 0
   hipError_t e;
   const int blocks = (int)std::min<int64_t>((n + 255) / 256, 4LL * c->cu);
@@ -340,9 +358,9 @@ int wcc_write_dofs(wcc_ctx* c, const double* host, int64_t n_cells, int parity, 
     e = wcc::launch_state_speed<float>(a, c->eq, P, blocks, c->stream);
   }
   if (e != hipSuccess) return fail(c, WCC_EDEVICE, "speed kernel: %s", hipGetErrorString(e));
-  HIPCHK(c, hipStreamSynchronize(c->stream));
   Ctrl back;
-  HIPCHK(c, hipMemcpy(&back, c->ctrl, sizeof back, hipMemcpyDeviceToHost));
+  int rc0 = read_ctrl(c, &back);
+  if (rc0) return rc0;
   c->written = true;
   c->parity_w = parity;
   c->launched = 0;

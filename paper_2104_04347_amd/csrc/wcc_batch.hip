@@ -49,7 +49,7 @@ template <int EQ, int P, bool LIM, class R>
 __device__ __forceinline__ void batch_tile(const BatchArgs<R>& a, const BatchInst& in, int first, int bc,
                                            Ctrl* ctrl, int lane, double& smax, unsigned& flags) {
   double dt;
-  const bool go = step_time(ctrl, a.slot, in.dx, 0.0, first == 0 && lane == 0, dt);
+  const bool go = step_time(ctrl, nullptr, a.slot, in.dx, 0.0, first == 0, dt);
   if (!go) return;
   StepArgs<R> s;
   s.p_old = a.p_in + in.p_off;
@@ -67,6 +67,7 @@ __device__ __forceinline__ void batch_tile(const BatchArgs<R>& a, const BatchIns
   s.dt_fixed = 0.0;
   s.ph = a.ph;
   s.ctrl = ctrl;
+  s.parts = nullptr;
   s.slot = a.slot;
   const double lam = dt / in.dx;
   if ((int64_t)first * 63 < s.n_new) run_tile<EQ, P, LIM, R>(s, first, lam, (R)(-lam), lane, smax, flags);
@@ -561,6 +562,7 @@ int wcc_batch_prepare(wcc_batch* b) {
       a.dx = in.dx;
       a.ph = b_phys<double>(b);
       a.ctrl = b->ctrl + i;
+      a.parts = nullptr;
       a.slot = 0;
       e = wcc::launch_state_speed<double>(a, b->eq, in.P, blocks, b->stream);
     } else {
@@ -574,6 +576,7 @@ int wcc_batch_prepare(wcc_batch* b) {
       a.dx = in.dx;
       a.ph = b_phys<float>(b);
       a.ctrl = b->ctrl + i;
+      a.parts = nullptr;
       a.slot = 0;
       e = wcc::launch_state_speed<float>(a, b->eq, in.P, blocks, b->stream);
     }

@@ -28,6 +28,14 @@ struct Ctrl {
 };
 static_assert(sizeof(Ctrl) == 192, "control block layout");
 
+// Partial wave-speed maxima of the single-instance kernels: 64 entries per
+// ring slot, one 64-byte line each, so the blocks of a launch spread their
+// atomics over 64 addresses instead of queueing on one; the next launch
+// reduces the 64 entries with one wave-wide max.
+constexpr int kSmaxParts = 64;
+constexpr int kSmaxStride = 8;  // unsigned long long per entry (64 bytes)
+constexpr size_t kSmaxPartsBytes = 3 * kSmaxParts * kSmaxStride * sizeof(unsigned long long);
+
 template <class R>
 struct StepArgs {
   const double* p_old;    // point values of the old mesh, [c][j]
@@ -42,6 +50,7 @@ struct StepArgs {
   double dt_fixed;        // > 0: fixed dt instead of the CFL step
   Phys<R> ph;
   Ctrl* ctrl;
+  unsigned long long* parts;  // partial maxima (single instance), or null: Ctrl::smax (batched)
   int32_t slot;
   int32_t pad;
 };

@@ -32,7 +32,7 @@ namespace wcc {
 template <int EQ, int P, bool LIM, class R, int PF>
 __global__ __launch_bounds__(256) void k_half_step(const StepArgs<R> a) {
   double dt;
-  if (!step_time(a.ctrl, a.slot, a.dx, a.dt_fixed, blockIdx.x == 0 && threadIdx.x == 0, dt)) return;
+  if (!step_time(a.ctrl, a.parts, a.slot, a.dx, a.dt_fixed, blockIdx.x == 0 && threadIdx.x < 64, dt)) return;
   const double lam = dt / a.dx;
   const R nlam = (R)(-lam);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
@@ -60,7 +60,7 @@ __global__ __launch_bounds__(256) void k_half_step(const StepArgs<R> a) {
       }
     }
   }
-  publish(a.ctrl, a.slot, smax, flags);
+  publish(a.ctrl, a.parts, a.slot, smax, flags);
 }
 
 // Largest wave speed of the stored state (first time step after a write).
@@ -86,7 +86,7 @@ __global__ __launch_bounds__(256) void k_state_speed(const StepArgs<R> a) {
     }
   }
   // publish into the CURRENT slot: pass slot-1 so that publish's "next" is slot
-  publish(a.ctrl, a.slot == 0 ? 2 : a.slot - 1, smax, flags);
+  publish(a.ctrl, a.parts, a.slot == 0 ? 2 : a.slot - 1, smax, flags);
 }
 
 // ---------------------------------------------------------------------------

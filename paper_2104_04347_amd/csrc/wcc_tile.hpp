@@ -37,20 +37,27 @@ __device__ __forceinline__ unsigned wave_or(unsigned v) {
 
 // Time-step bookkeeping shared by the single and batched kernels.  Returns
 // false when this launch must do nothing (end time reached or a flag raised
-// by an earlier step); in that case the slot is propagated unchanged.
-__device__ __forceinline__ bool step_time(Ctrl* ctrl, int slot, double dx, double dt_fixed, bool leader,
-                                          double& dt) {
+// by an earlier step); in that case the slot is propagated unchanged.  With
+// `parts` (single-instance kernels) the wave speed of the previous step is
+// the max of the 64 partial entries of the slot; the first wave of block 0
+// (`leader_wave`) maintains the ring.  Called by every lane of every wave.
+__device__ __forceinline__ bool step_time(Ctrl* ctrl, unsigned long long* parts, int slot, double dx,
+                                          double dt_fixed, bool leader_wave, double& dt) {
   const int s1 = slot == 2 ? 0 : slot + 1;
   const int s2 = s1 == 2 ? 0 : s1 + 1;
+  const int lane = threadIdx.x & 63;
   const double t = ctrl->t[slot];
   const unsigned flags_in = ctrl->flags[slot];
   bool done = flags_in != 0u;
   double tn;
+  unsigned long long mine = 0ull;  // this lane's partial entry of the slot (parts mode)
+  if (parts) mine = parts[(slot * kSmaxParts + lane) * kSmaxStride];
   if (dt_fixed > 0.0) {
     dt = dt_fixed;
     tn = t + dt;
   } else {
-    const double smax = __longlong_as_double((long long)ctrl->smax[slot]);
+    const double smax = parts ? wave_max(__longlong_as_double((long long)mine))
+                              : __longlong_as_double((long long)ctrl->smax[slot]);
     const double tend = ctrl->t_end;
     done = done || !(t < tend);
     dt = (ctrl->cfl * dx) / smax;
@@ -62,24 +69,35 @@ __device__ __forceinline__ bool step_time(Ctrl* ctrl, int slot, double dx, doubl
       tn = t + dt;
     }
   }
-  if (leader) {
-    if (done) {
-      ctrl->t[s1] = t;
-      ctrl->smax[s1] = ctrl->smax[slot];
-      ctrl->flags[s1] = flags_in;
-    } else {
-      ctrl->t[s1] = tn;
-      ctrl->steps_done += 1;
+  if (leader_wave) {
+    if (parts) {
+      // Slot s1 was cleared by the previous launch (as its s2) and is being
+      // raised by the other blocks' atomics now; only a finished run, where
+      // no block publishes, carries the maximum forward.
+      if (done) parts[(s1 * kSmaxParts + lane) * kSmaxStride] = mine;
+      parts[(s2 * kSmaxParts + lane) * kSmaxStride] = 0ull;
     }
-    ctrl->smax[s2] = 0ull;
-    ctrl->flags[s2] = 0u;
+    if (lane == 0) {
+      if (done) {
+        ctrl->t[s1] = t;
+        ctrl->smax[s1] = ctrl->smax[slot];
+        ctrl->flags[s1] = flags_in;
+      } else {
+        ctrl->t[s1] = tn;
+        ctrl->steps_done += 1;
+      }
+      ctrl->smax[s2] = 0ull;
+      ctrl->flags[s2] = 0u;
+    }
   }
   return !done;
 }
 
-// Per-block reduction of the wave speeds and flags, then one atomic each,
-// skipped when it cannot raise the stored maximum.
-__device__ __forceinline__ void publish(Ctrl* ctrl, int slot, double smax, unsigned flags) {
+// Per-block reduction of the wave speeds and flags, then one atomic each into
+// the next slot, skipped when it cannot raise the stored maximum.  With
+// `parts` the block's atomic goes to entry (block index mod 64).
+__device__ __forceinline__ void publish(Ctrl* ctrl, unsigned long long* parts, int slot, double smax,
+                                        unsigned flags) {
   __shared__ double red_s[16];
   __shared__ unsigned red_f[16];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
@@ -97,8 +115,9 @@ __device__ __forceinline__ void publish(Ctrl* ctrl, int slot, double smax, unsig
     }
     const int s1 = slot == 2 ? 0 : slot + 1;
     const unsigned long long bits = (unsigned long long)__double_as_longlong(smax);
-    if (bits > __hip_atomic_load(&ctrl->smax[s1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
-      atomicMax(&ctrl->smax[s1], bits);
+    unsigned long long* dst =
+        parts ? &parts[(s1 * kSmaxParts + (int)(blockIdx.x % kSmaxParts)) * kSmaxStride] : &ctrl->smax[s1];
+    if (bits > __hip_atomic_load(dst, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicMax(dst, bits);
     if (flags) atomicOr(&ctrl->flags[s1], flags);
   }
 }
