@@ -34,19 +34,6 @@ FP32_VALU_PEAK = 157.3e12  # flop/s (packed / dual-issue)
 CFL_BY_P = [0.4, 0.4, 0.3, 0.25, 0.25]
 
 
-def kernel_source_hash() -> str:
-    """SHA-256 over the HIP sources and headers of the kernels (traffic figures
-    measured with counters are only reported for the kernel they were taken on)."""
-    import hashlib
-    h = hashlib.sha256()
-    d = os.path.join(ROOT, "paper_2104_04347_amd", "csrc")
-    for name in sorted(os.listdir(d)):
-        if name.endswith((".hip", ".hpp")):
-            with open(os.path.join(d, name), "rb") as f:
-                h.update(name.encode() + b"\0" + f.read())
-    return h.hexdigest()
-
-
 def measured_traffic(kernel: str, N: int):
     """HBM bytes per launch from the committed counter record (FETCH_SIZE and
     WRITE_SIZE, scaled by the copy-kernel calibration), or None when the
@@ -57,6 +44,7 @@ def measured_traffic(kernel: str, N: int):
             rec = json.load(f)
     except (OSError, ValueError):
         return None
+    from paper_2104_04347_amd.profsum import kernel_source_hash
     e = rec.get(kernel)
     if not e or e.get("source_sha256") != kernel_source_hash() or e.get("N") != N:
         return None
@@ -88,11 +76,27 @@ def bytes_per_launch(N: int, P: int, nc: int, precision: str) -> float:
     return float(n_old_plus_new * b_cell)
 
 
+def launch_shape_single(args, s, q0) -> dict:
+    """Launch shape of the single-instance kernel: a cached autotuner result
+    when there is one (and --tune is not 'force'), else tune now (--tune off:
+    the library's default).  Results do not depend on the shape."""
+    from paper_2104_04347_amd import autotune
+    if args.tune == "off":
+        return {"threads": 0, "blocks": 0, "variant": 0, "source": "library default"}
+    if args.tune == "auto" and autotune.apply_single(s):
+        c = autotune.cached_single(s)
+        return {"threads": c["threads"], "blocks": c["blocks"], "variant": c.get("variant", 0),
+                "source": "autotune cache"}
+    best = autotune.tune_single(s, q0, args.cfl)
+    return {"threads": best["threads"], "blocks": best["blocks"], "variant": best["variant"], "source": "autotuned"}
+
+
 def time_single(args, precision: str, q0):
     import torch
     from paper_2104_04347_amd import binding
     P, N = args.P, args.N
     s = binding.Solver("euler", P, N, "transmissive", limiter=True, precision=precision)
+    shape = launch_shape_single(args, s, q0)
     s.write(q0)
     s.run(args.warmup, args.cfl)
     torch.cuda.synchronize()
@@ -113,7 +117,7 @@ def time_single(args, precision: str, q0):
     cells = cells_updated(N, "transmissive", parity0, args.steps)
     dofs = cells * 3 * (P + 1)
     out = dict(value=dofs / wall, wall_s=wall, event_ms=ev_ms, lib_event_ms=lib_ms, flags=int(info.flags),
-               ok=ok, t=info.t, half_steps=int(info.half_steps))
+               ok=ok, t=info.t, half_steps=int(info.half_steps), launch=shape)
     s.close()
     return out
 
@@ -123,13 +127,27 @@ def time_batch(args):
     from paper_2104_04347_amd import binding, inputs
     spec = inputs.batch_spec(args.batch_B, args.seed)
     bt = binding.Batch("euler", spec.P, spec.N, "transmissive", limiter=True, precision="fp32_mixed")
+    from paper_2104_04347_amd import autotune
+
+    def load_instances(again=False):
+        if again:
+            bt.rebind()
+        for b in range(spec.P.size):
+            bt.write(b, inputs.batch_instance(spec, b))
+        bt.prepare()
+
+    load_instances()
     sched = None
     if args.batch_schedule:
         sched = [int(v) for v in args.batch_schedule.split(",")]
         bt.set_schedule(*sched)
-    for b in range(spec.P.size):
-        bt.write(b, inputs.batch_instance(spec, b))
-    bt.prepare()
+    elif args.tune != "off":
+        c = autotune.cached_batch(bt) if args.tune == "auto" else None
+        if c is None:
+            c = autotune.tune_batch(bt, CFL_BY_P)
+            load_instances(again=True)            # time from the initial state again
+        sched = [c["threads"], c["blocks"], c["mode"]]
+        bt.set_schedule(*sched)
     bt.run(args.batch_warmup, CFL_BY_P)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -214,8 +232,8 @@ def cpu_baseline(args, q0):
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1000, help="timed half-steps")
-    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--steps", type=int, default=2000, help="timed half-steps")
+    ap.add_argument("--warmup", type=int, default=480, help="untimed half-steps first (clocks settle, graphs built)")
     ap.add_argument("--P", type=int, default=3)
     ap.add_argument("--N", type=int, default=1 << 20)
     ap.add_argument("--cfl", type=float, default=0.25)
@@ -231,6 +249,8 @@ def main():
     ap.add_argument("--large", action="store_true", help="also run the large 16.7M-cell P=4 workload")
     ap.add_argument("--large-N", type=int, default=1 << 24)
     ap.add_argument("--large-steps", type=int, default=10000)
+    ap.add_argument("--tune", choices=("auto", "force", "off"), default="auto",
+                    help="launch shapes: cached autotuner result else tune (auto), always tune, or library default")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="also run 5 device-to-device copies of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -324,6 +344,7 @@ def main():
                                f"+ density sine, transmissive, limiter on, CFL {args.cfl} per half-step",
                    "N": args.N, "P": args.P, "precision": "fp64", "parallelism": "single GPU"},
         "valid": bool(r64["ok"]),
+        "launch": r64["launch"],
         "roofline": roofline,
     }
     if rmx is not None:
@@ -331,7 +352,8 @@ def main():
         line["fp32_mixed"] = {"value": rmx["value"], "unit": "cell-DOF updates/s", "dtype": "f32 bulk + f64 average",
                               "ms_per_step": rmx["wall_s"] * 1e3 / args.steps, "valid": bool(rmx["ok"]),
                               "launch_us": round(rm["launch_us"], 2), "hbm_frac": round(rm["hbm_frac"], 4),
-                              "gbs": round(rm["gbs"], 1), "tflops": round(rm["tflops"], 3)}
+                              "gbs": round(rm["gbs"], 1), "tflops": round(rm["tflops"], 3),
+                              "launch": rmx["launch"]}
     if rb is not None:
         line["batched"] = rb
     if rl is not None:

@@ -52,10 +52,11 @@ def key_single(equation: str, P: int, N: int, precision: str, limiter: bool) -> 
 
 
 def tune_single(solver: "binding.Solver", q0: np.ndarray, cfl: float, steps: int = 480,
-                threads=(64, 128, 256), block_factors=(0, 1, 2, 3, 4, 8), variants=(0, 1),
+                threads=(128, 256), block_factors=(0, 2, 3, 4, 5, 6, 8), variants=(0, 1),
                 verbose: bool = False) -> dict:
     """Time the candidate shapes on `solver` (state q0, CFL cfl); keep the best.
-    block factor 0 = the library's default (resident-block capacity)."""
+    Blocks per launch = block factor x compute units; factor 0 = the
+    library's default (resident-block capacity)."""
     import torch
     cu = torch.cuda.get_device_properties(0).multi_processor_count
     results = []
@@ -92,6 +93,22 @@ def tune_single(solver: "binding.Solver", q0: np.ndarray, cfl: float, steps: int
     return best
 
 
+def cached_single(solver: "binding.Solver"):
+    """The cached shape for `solver`'s configuration, or None."""
+    return _load_cache().get(key_single(solver.equation, solver.P, solver.N,
+                                        binding.PRECISIONS_NAME[solver.params.precision],
+                                        bool(solver.params.limiter)))
+
+
+def key_batch(batch: "binding.Batch") -> str:
+    return f"batch/B{batch.B}/{binding.PRECISIONS_NAME[batch.params.precision]}"
+
+
+def cached_batch(batch: "binding.Batch"):
+    """The cached schedule for `batch`'s size and precision, or None."""
+    return _load_cache().get(key_batch(batch))
+
+
 def apply_single(solver: "binding.Solver") -> bool:
     """Apply a cached shape to `solver` if one exists; returns whether it did."""
     k = key_single(solver.equation, solver.P, solver.N, binding.PRECISIONS_NAME[solver.params.precision],
@@ -126,7 +143,7 @@ def tune_batch(batch: "binding.Batch", cfl_by_P, steps: int = 24, modes=(1, 2),
     best = min(results, key=lambda r: r["ms_per_step"])
     batch.set_schedule(best["threads"], best["blocks"], best["mode"])
     c = _load_cache()
-    c[f"batch/B{batch.B}/{binding.PRECISIONS_NAME[batch.params.precision]}"] = {
+    c[key_batch(batch)] = {
         k: best[k] for k in ("mode", "threads", "blocks", "ms_per_step")}
     _save_cache(c)
     best["tried"] = results
