@@ -78,7 +78,10 @@ __device__ __forceinline__ void batch_tile(const BatchArgs<R>& a, const BatchIns
 template <int EQ, int PSEL, bool LIM, class R>
 __global__ __launch_bounds__(256) void k_batch_step(const BatchArgs<R> a, const int64_t* __restrict__ block_start,
                                                     int bc) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  // the wave index is the same in every lane: say so, so that tile and
+  // instance indices live in scalar registers
+  const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6),
+            nw = blockDim.x >> 6;
   const int64_t t0 = block_start[blockIdx.x], t1 = block_start[blockIdx.x + 1];
   int cur = -1;
   double smax = 0.0;

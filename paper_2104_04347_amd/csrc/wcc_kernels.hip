@@ -35,7 +35,10 @@ __global__ __launch_bounds__(256) void k_half_step(const StepArgs<R> a) {
   if (!step_time(a.ctrl, a.parts, a.slot, a.dx, a.dt_fixed, blockIdx.x == 0 && threadIdx.x < 64, dt)) return;
   const double lam = dt / a.dx;
   const R nlam = (R)(-lam);
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  // the wave index is the same in every lane: say so, so that tile and
+  // instance indices live in scalar registers
+  const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6),
+            nw = blockDim.x >> 6;
   const int64_t tiles = (a.n_new + 62) / 63;
   const int64_t per_block = (tiles + gridDim.x - 1) / gridDim.x;
   const int64_t t_begin = (int64_t)blockIdx.x * per_block;

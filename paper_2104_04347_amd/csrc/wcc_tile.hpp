@@ -133,6 +133,32 @@ __device__ __forceinline__ void row_store(T* base, uint32_t i, T v) {
   *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + (uint32_t)(i * (uint32_t)sizeof(T))) = v;
 }
 
+// Base pointer of one row, made opaque in a scalar register pair.  Without
+// this the compiler folds the row offset (row x ld) into a 64-bit per-lane
+// address, two vector instructions per load or store; with it every access
+// is one instruction with an SGPR base and the lane's 32-bit offset.  The
+// pointer must be uniform across the wavefront (it is: one wave handles one
+// tile of one instance).
+template <class T>
+using global_ptr = __attribute__((address_space(1))) T*;
+
+template <class T>
+__device__ __forceinline__ global_ptr<T> row_base(T* p) {
+  const uint64_t v = reinterpret_cast<uint64_t>(p);
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v), hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+  global_ptr<T> g = (global_ptr<T>)reinterpret_cast<T*>(((uint64_t)hi << 32) | lo);
+  asm("" : "+s"(g));
+  return g;
+}
+template <class T>
+__device__ __forceinline__ T row_at(global_ptr<const T> base, uint32_t i) {
+  return *(global_ptr<const T>)((global_ptr<const char>)base + (uint32_t)(i * (uint32_t)sizeof(T)));
+}
+template <class T>
+__device__ __forceinline__ void row_store(global_ptr<T> base, uint32_t i, T v) {
+  *(global_ptr<T>)((global_ptr<char>)base + (uint32_t)(i * (uint32_t)sizeof(T))) = v;
+}
+
 // Load the old cell `o` (already mapped into [0, n_old)), or a Dirichlet ghost.
 template <int EQ, int P, class R>
 __device__ __forceinline__ void load_cell(const double* __restrict__ pv, const R* __restrict__ dv, int64_t ld,
@@ -160,8 +186,7 @@ __device__ __forceinline__ void load_cell(const double* __restrict__ pv, const R
 // Map the lane's old-cell index onto storage: periodic wrap, transmissive
 // copies of the end cells for the ghosts of the odd->even step, Dirichlet
 // ghost states, clamping for lanes past the end (their results are unused).
-__device__ __forceinline__ int64_t map_old(int64_t o, int64_t n_old, int64_t N, int bc, int parity_old,
-                                           int& ghost) {
+__device__ __forceinline__ int map_old(int o, int n_old, int N, int bc, int parity_old, int& ghost) {
   ghost = 0;
   if (bc == kPeriodic) {
     // a tile reaches at most one cell before 0 and 63 past the end, so one
@@ -193,17 +218,18 @@ struct TileIn {
 template <int EQ, int P, class R>
 __device__ __forceinline__ void fetch_tile(const StepArgs<R>& a, int64_t tile, int lane, TileIn<EQ, P, R>& in) {
   constexpr int NC = ncomp<EQ>();
-  const int64_t j0 = tile * 63;
+  // cell indices fit 32 bits (N <= 2^28, checked at creation)
+  const int j0 = (int)tile * 63;
   int ghost;
-  const int64_t o = map_old(j0 + lane - (a.parity_old == 1 ? 1 : 0), a.n_old, a.N, a.bc, a.parity_old, ghost);
+  const int o = map_old(j0 + lane - (a.parity_old == 1 ? 1 : 0), (int)a.n_old, (int)a.N, a.bc, a.parity_old, ghost);
   // rows addressed by a uniform 64-bit base and a 32-bit byte offset (rows
   // are shorter than 4 GiB, checked at creation)
 #pragma unroll
   for (int c = 0; c < NC; ++c) {
-    in.p[c] = row_at(a.p_old + c * a.ld, (uint32_t)o);
+    in.p[c] = row_at(row_base(a.p_old + c * a.ld), (uint32_t)o);
     in.d[c][0] = (R)0;
 #pragma unroll
-    for (int k = 1; k <= P; ++k) in.d[c][k] = row_at(a.d_old + (c * P + (k - 1)) * a.ld, (uint32_t)o);
+    for (int k = 1; k <= P; ++k) in.d[c][k] = row_at(row_base(a.d_old + (c * P + (k - 1)) * a.ld), (uint32_t)o);
   }
   if (ghost) {
     const double* g = a.ctrl->ghost[ghost - 1];
@@ -238,8 +264,8 @@ __device__ __forceinline__ void compute_tile(const StepArgs<R>& a, int64_t tile,
     if (P == 0) V_R[c][0] = (R)0;
   }
 
-  const int64_t j = tile * 63 + lane;
-  if (lane < 63 && j < a.n_new) {
+  const int j = (int)tile * 63 + lane;
+  if (lane < 63 && j < (int)a.n_new) {
     double pn[NC];
     R dn[NC][P + 1];
     double sp;
@@ -248,9 +274,9 @@ __device__ __forceinline__ void compute_tile(const StepArgs<R>& a, int64_t tile,
     if (!(sp == sp)) smax = sp;
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
-      row_store(a.p_new + c * a.ld, (uint32_t)j, pn[c]);
+      row_store(row_base(a.p_new + c * a.ld), (uint32_t)j, pn[c]);
 #pragma unroll
-      for (int k = 1; k <= P; ++k) row_store(a.d_new + (c * P + (k - 1)) * a.ld, (uint32_t)j, dn[c][k]);
+      for (int k = 1; k <= P; ++k) row_store(row_base(a.d_new + (c * P + (k - 1)) * a.ld), (uint32_t)j, dn[c][k]);
     }
   }
 }
