@@ -167,6 +167,28 @@ def time_batch(args):
                 schedule=sched or "default")
 
 
+def cpu_baseline_batch(args):
+    """The FP64 oracle, single-threaded, on one half-step of every instance of
+    the batched workload (the cost of a half-step does not depend on which one
+    it is, so solves/s for `batch_steps` half-steps is extrapolated from it)."""
+    import oracle
+    from paper_2104_04347_amd import inputs
+    spec = inputs.batch_spec(args.batch_B, args.seed)
+    wall, dofs = 0.0, 0
+    for b in range(spec.P.size):
+        P, N = int(spec.P[b]), int(spec.N[b])
+        q0 = inputs.batch_instance(spec, b)
+        pb = oracle.Problem("euler", P, N, bc="transmissive", limiter=True)
+        t0 = time.perf_counter()
+        oracle.run(pb, q0, cfl=CFL_BY_P[P], max_half_steps=1)
+        wall += time.perf_counter() - t0
+        dofs += cells_updated(N, "transmissive", 0, 1) * 3 * (P + 1)
+    return {"value": spec.P.size / (wall * args.batch_steps), "unit": "solves/s",
+            "cell_dof_per_s": dofs / wall, "cores": 1, "kind": "oracle",
+            "sample": f"one half-step of each of the {spec.P.size} instances ({wall:.1f} s of oracle time, "
+                      f"single thread), scaled to {args.batch_steps} half-steps per solve"}
+
+
 def time_large(args):
     """Large 1D Euler: N = 16,777,216, P = 4, 8 seeded jumps with 9 states and
     the density sine, periodic, CFL 0.20 per half-step, `large_steps`
@@ -198,6 +220,16 @@ def time_large(args):
                      "drift_rel": [float(abs(a - b) / c) for a, b, c in zip(tot, tot0, abs0)]}
         del q
         s.close()
+    if not args.no_cpu and args.large_cpu_steps > 0:
+        import oracle
+        pb = oracle.Problem("euler", P, N, bc="periodic", limiter=True)
+        t0 = time.perf_counter()
+        r = oracle.run(pb, q0, cfl=cfl, max_half_steps=args.large_cpu_steps)
+        wall = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": N * 3 * (P + 1) * r.half_steps / wall, "unit": "cell-DOF updates/s",
+                               "cores": 1, "kind": "oracle",
+                               "sample": f"first {r.half_steps} half-steps of the large workload, FP64 oracle, "
+                                         f"single thread, {wall:.1f} s"}
     d = finals["fp32_mixed"] - finals["fp64"]
     scale = np.abs(finals["fp64"]).max(axis=1)
     out["mixed_vs_fp64_point_values"] = {"L1_rel": [float(np.abs(d[c]).mean() / scale[c]) for c in range(3)],
@@ -246,6 +278,9 @@ def main():
     ap.add_argument("--batch-warmup", type=int, default=24)
     ap.add_argument("--batch-schedule", default="", help="threads,blocks,mode for the batched kernels")
     ap.add_argument("--cpu-steps", type=int, default=24)
+    ap.add_argument("--large-cpu-steps", type=int, default=5, help="oracle half-steps timed on the large workload")
+    ap.add_argument("--seeds", default="0,1,2,3,4",
+                    help="also time the FP64 and mixed legs on these seeds of the same workload ('' for none)")
     ap.add_argument("--large", action="store_true", help="also run the large 16.7M-cell P=4 workload")
     ap.add_argument("--large-N", type=int, default=1 << 24)
     ap.add_argument("--large-steps", type=int, default=10000)
@@ -276,6 +311,18 @@ def main():
     if not args.no_mixed:
         rmx = time_single(args, "fp32_mixed", q0)
         print(f"[bench] fp32_mixed: {rmx['value']:.3e} DOF/s", file=sys.stderr, flush=True)
+    seeds_out = {}
+    for sd in [int(v) for v in args.seeds.split(",") if v.strip()]:
+        if sd == args.seed:
+            continue
+        qs, _ = inputs.euler_riemann(sd, args.P, args.N)
+        e = {"fp64": time_single(args, "fp64", qs)["value"]}
+        if not args.no_mixed:
+            e["fp32_mixed"] = time_single(args, "fp32_mixed", qs)["value"]
+        seeds_out[str(sd)] = e
+        print(f"[bench] seed {sd}: fp64 {e['fp64']:.3e} DOF/s", file=sys.stderr, flush=True)
+    if seeds_out:
+        seeds_out[str(args.seed)] = {"fp64": r64["value"], **({"fp32_mixed": rmx["value"]} if rmx else {})}
     rb = None
     if not args.no_batch:
         rb = time_batch(args)
@@ -358,9 +405,14 @@ def main():
         line["batched"] = rb
     if rl is not None:
         line["large"] = rl
+    if seeds_out:
+        line["seeds"] = seeds_out
     if not args.no_cpu:
         print("[bench] CPU baseline (oracle) ...", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(args, q0)
+        if rb is not None:
+            print("[bench] CPU baseline, batched workload (oracle) ...", file=sys.stderr, flush=True)
+            line["batched"]["cpu_baseline"] = cpu_baseline_batch(args)
     print(json.dumps(line), flush=True)
 
 

@@ -39,12 +39,16 @@ def _load_cache() -> dict:
 
 
 def _save_cache(c: dict) -> None:
+    """Best effort: a cache that cannot be written only costs a re-tune."""
     p = cache_path()
-    os.makedirs(os.path.dirname(p), exist_ok=True)
-    tmp = p + ".tmp"
-    with open(tmp, "w") as f:
-        json.dump(c, f, indent=1, sort_keys=True)
-    os.replace(tmp, p)
+    try:
+        os.makedirs(os.path.dirname(p) or ".", exist_ok=True)
+        tmp = p + ".tmp"
+        with open(tmp, "w") as f:
+            json.dump(c, f, indent=1, sort_keys=True)
+        os.replace(tmp, p)
+    except OSError:
+        pass
 
 
 def key_single(equation: str, P: int, N: int, precision: str, limiter: bool) -> str:
