@@ -100,6 +100,7 @@ class EulerPiecewise:
     sine_w: float = 5.0
     period: tuple | None = None   # (x_left, x_right) when the data wraps around
     wrap_jump: bool = True        # periodic data: the state jumps at x_left == x_right
+    piece_sine: np.ndarray | None = None   # per-piece factor on sine_amp (None: 1 everywhere)
 
     def piece(self, x: np.ndarray) -> np.ndarray:
         return np.searchsorted(self.breaks, x, side="right")
@@ -116,10 +117,11 @@ class EulerPiecewise:
         i = self.piece(xw)
         rs, us, ps = self.rho[i], self.u[i], self.p[i]
         w = self.sine_w
+        amp = self.sine_amp if self.piece_sine is None else self.sine_amp * np.asarray(self.piece_sine)[i]
         if k == 0:
-            rho = rs * (1.0 + self.sine_amp * np.sin(w * xw))
+            rho = rs * (1.0 + amp * np.sin(w * xw))
             return np.stack([rho, rho * us, ps / (self.gamma - 1.0) + 0.5 * rho * us * us])
-        drho = rs * self.sine_amp * w ** k * np.sin(w * xw + k * np.pi / 2)
+        drho = rs * amp * w ** k * np.sin(w * xw + k * np.pi / 2)
         return np.stack([drho, drho * us, 0.5 * drho * us * us])
 
     def cell_mean(self, xa: float, xb: float) -> np.ndarray:
@@ -261,3 +263,92 @@ def batch_spec(B: int, seed: int, n_lo: int = 256, n_hi: int = 65536, degrees=(1
 def batch_instance(spec: BatchSpec, b: int, gamma: float = 1.4):
     """Riemann problem with density sine on [0, 1], transmissive, for instance b."""
     return euler_riemann(int(spec.seeds[b]), int(spec.P[b]), int(spec.N[b]), gamma=gamma)[0]
+
+
+# ---------------------------------------------------------------------------
+# The 1D experiments of Section 5 (problem data only)
+# ---------------------------------------------------------------------------
+def sod(P: int, N: int, parity: int = 0):
+    """Sod's shock tube (Section 5.2): [0, 2], (rho, u, p) = (1, 0, 1) for
+    x < 1 and (0.125, 0, 0.1) otherwise, transmissive boundaries."""
+    data = EulerPiecewise(np.array([1.0]), np.array([1.0, 0.125]), np.array([0.0, 0.0]), np.array([1.0, 0.1]),
+                          sine_amp=0.0)
+    x = centers(0.0, 2.0, N, n_cells(N, "transmissive", parity), parity)
+    return euler_taylor(data, x, 2.0 / N, P), data
+
+
+def shu_osher_tt(P: int, N: int, parity: int = 0):
+    """Titarev and Toro's modified Shu-Osher problem (Section 5.2): [-5, 5],
+    (1.515695, 0.523346, 1.805) for x < -4.5, else (1 + 0.1 sin(20 pi x), 0, 1),
+    transmissive boundaries."""
+    data = EulerPiecewise(np.array([-4.5]), np.array([1.515695, 1.0]), np.array([0.523346, 0.0]),
+                          np.array([1.805, 1.0]), sine_amp=0.1, sine_w=20.0 * np.pi,
+                          piece_sine=np.array([0.0, 1.0]))
+    x = centers(-5.0, 5.0, N, n_cells(N, "transmissive", parity), parity)
+    return euler_taylor(data, x, 10.0 / N, P), data
+
+
+def jiang_shu_u0(x: np.ndarray) -> np.ndarray:
+    """Jiang and Shu's composite profile on [-1, 1] (Section 5.1): Gaussians,
+    a square wave, a sharp triangle and a half ellipse, zero elsewhere."""
+    x = np.asarray(x, dtype=np.float64)
+    a, z, dl, al = 0.5, -0.7, 0.005, 10.0
+    be = np.log(2.0) / (36.0 * dl * dl)
+    G = lambda zz: np.exp(-be * (x - zz) ** 2)
+    F = lambda aa: np.sqrt(np.maximum(1.0 - al * al * (x - aa) ** 2, 0.0))
+    u = np.zeros_like(x)
+    m = (x >= -0.8) & (x <= -0.6)
+    u = np.where(m, (G(z - dl) + 4.0 * G(z) + G(z + dl)) / 6.0, u)
+    u = np.where((x >= -0.4) & (x <= -0.2), 1.0, u)
+    u = np.where((x >= 0.0) & (x <= 0.2), 1.0 - 10.0 * np.abs(x - 0.1), u)
+    u = np.where((x >= 0.4) & (x <= 0.6), (F(a - dl) + 4.0 * F(a) + F(a + dl)) / 6.0, u)
+    return u
+
+
+# points where the composite profile jumps or loses smoothness
+JIANG_SHU_BREAKS = np.array([-0.8, -0.6, -0.4, -0.2, 0.0, 0.1, 0.2, 0.4, 0.405, 0.595, 0.6])
+
+
+def projected_scalar(u0, breaks: np.ndarray, x: np.ndarray, dx: float, P: int) -> np.ndarray:
+    """Degree-P L2 projection of u0 onto each cell (Gauss-Legendre quadrature,
+    split at the given break points), returned as the point value and scaled
+    derivatives at the cell centre -- the state convention of this module.
+    Used for data that is not smooth enough for Taylor expansion."""
+    n = x.size
+    s_of = np.polynomial.legendre
+    coef = np.zeros((P + 1, n))
+    xa, xb = x - 0.5 * dx, x + 0.5 * dx
+
+    def accumulate(j, lo, hi):
+        mid, half = 0.5 * (lo + hi), 0.5 * (hi - lo)
+        xs = mid[:, None] + half[:, None] * _GL_X[None, :]
+        sv = 2.0 * (xs - x[j][:, None]) / dx               # Legendre variable on [-1, 1]
+        uv = u0(xs)
+        wv = half[:, None] * _GL_W[None, :] / dx            # weights of the cell mean
+        for m in range(P + 1):
+            e = np.zeros(m + 1)
+            e[m] = 1.0
+            coef[m, j] += (2 * m + 1) * np.sum(wv * uv * s_of.legval(sv, e), axis=1)
+
+    split = np.zeros(n, dtype=bool)
+    for b in breaks:
+        split |= (xa < b) & (b < xb)
+    plain = np.nonzero(~split)[0]
+    accumulate(plain, xa[plain], xb[plain])
+    for j in np.nonzero(split)[0]:
+        pts = [xa[j]] + sorted(b for b in breaks if xa[j] < b < xb[j]) + [xb[j]]
+        for lo, hi in zip(pts[:-1], pts[1:]):
+            accumulate(np.array([j]), np.array([lo]), np.array([hi]))
+    q = np.empty((1, P + 1, n))
+    for j in range(n):
+        mono = s_of.leg2poly(coef[:, j])                    # coefficients of s^k, s = 2 xi
+        for k in range(P + 1):
+            ak = (mono[k] if k < mono.size else 0.0) * 2.0 ** k
+            q[0, k, j] = ak * float(np.prod(np.arange(1, k + 1)))   # u_kx = k! a_k
+    return q
+
+
+def jiang_shu(P: int, N: int):
+    """Projected Jiang-Shu composite on N periodic cells of [-1, 1]."""
+    x = centers(-1.0, 1.0, N, N, 0)
+    return projected_scalar(jiang_shu_u0, JIANG_SHU_BREAKS, x, 2.0 / N, P)

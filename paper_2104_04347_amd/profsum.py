@@ -33,13 +33,16 @@ CSRC = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
 COPY_KERNEL = "__amd_rocclr_copyBuffer"
 
 
+# the sources the single-instance 1D half-step kernel is compiled from
+KERNEL_SOURCES = ("wcc_cell.hpp", "wcc_internal.hpp", "wcc_kernels.hip", "wcc_tile.hpp")
+
+
 def kernel_source_hash() -> str:
-    """SHA-256 over the HIP sources and headers of the kernels."""
+    """SHA-256 over the sources of the 1D half-step kernel."""
     h = hashlib.sha256()
-    for name in sorted(os.listdir(CSRC)):
-        if name.endswith((".hip", ".hpp")):
-            with open(os.path.join(CSRC, name), "rb") as f:
-                h.update(name.encode() + b"\0" + f.read())
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(CSRC, name), "rb") as f:
+            h.update(name.encode() + b"\0" + f.read())
     return h.hexdigest()
 
 

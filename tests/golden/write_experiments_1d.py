@@ -1,0 +1,149 @@
+"""Writes tests/golden/experiments_1d.json from the FP64 oracle alone.
+
+The 1D experiments of Section 5 of the paper, run with the CFL numbers of
+Section 5 (0.4 / 0.3 / 0.25 per half-step for WCCS-2 / 3 / 4), limiter on:
+
+* Jiang-Shu composite advection (Section 5.1): [-1, 1] periodic, 400 cells,
+  t = 12; errors against the exact solution (the initial profile: the period
+  is 2, so the solution at t = 12 is u0).
+* Sod shock tube (Section 5.2): [0, 2] transmissive, dx = 1/100, t = 0.4;
+  density errors against the exact Riemann solution.
+* Titarev-Toro modified Shu-Osher problem (Section 5.2): [-5, 5]
+  transmissive, dx = 1/200, t = 5; density errors against our own fine-grid
+  run (oracle, WCCS-4, dx = 1/1000; the paper's reference is a WENO-Z run on
+  the same dx, a comparison system outside this build).
+
+Recorded per run: the number of half-steps, the final parity and time, the
+SHA-256 of the final state (float64, C order, shape (nc, P+1, n)) so that a
+GPU run can be checked bit for bit without re-running the oracle, and the
+error norms.  The fine reference density is stored as float32.
+
+Run from the repository root:  python tests/golden/write_experiments_1d.py
+"""
+from __future__ import annotations
+
+import base64
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+sys.path.insert(0, ROOT)
+sys.path.insert(0, os.path.join(ROOT, "tests"))
+
+import oracle                                    # noqa: E402
+from paper_2104_04347_amd import inputs          # noqa: E402
+import exact                                     # noqa: E402
+
+CFL = {1: 0.4, 2: 0.3, 3: 0.25}
+OUT = os.path.join(os.path.dirname(os.path.abspath(__file__)), "experiments_1d.json")
+
+# windows (closed intervals) over which regional errors are reported
+JS_REGIONS = {"gauss": (-0.85, -0.55), "square": (-0.45, -0.15), "triangle": (-0.05, 0.25),
+              "ellipse": (0.35, 0.65)}
+SOD_CONTACT = (1.27, 1.47)        # exact contact at x = 1 + 0.9274526 * 0.4 = 1.371
+TT_WAVES = (0.5, 2.2)             # compressed entropy waves behind the shock at t = 5
+
+
+def state_sha(q: np.ndarray) -> str:
+    return hashlib.sha256(np.ascontiguousarray(q, dtype=np.float64).tobytes()).hexdigest()
+
+
+def region_mean(err, x, lo, hi):
+    m = (x >= lo) & (x <= hi)
+    return float(err[m].mean())
+
+
+def jiang_shu():
+    out = {}
+    for P in (1, 2, 3):
+        N = 400
+        q0 = inputs.jiang_shu(P, N)
+        pb = oracle.Problem("advection", P, N, bc="periodic", limiter=True, x_left=-1.0, x_right=1.0)
+        r = oracle.run(pb, q0, t_end=12.0, cfl=CFL[P])
+        x = inputs.centers(-1.0, 1.0, N, N, r.parity)
+        u = r.q[0, 0]
+        err = np.abs(u - inputs.jiang_shu_u0(x))
+        out[f"P{P}"] = {
+            "N": N, "half_steps": r.half_steps, "parity": r.parity, "t": r.t, "flags": r.flags,
+            "sha256": state_sha(r.q), "L1": float(err.mean()), "Linf": float(err.max()),
+            "regions": {k: region_mean(err, x, *w) for k, w in JS_REGIONS.items()},
+            "square_transition_cells": [int(((np.abs(x - e) < 0.1) & (u > 0.1) & (u < 0.9)).sum())
+                                        for e in (-0.4, -0.2)],
+        }
+    return out
+
+
+def sod():
+    out = {}
+    WL, WR = (1.0, 0.0, 1.0), (0.125, 0.0, 0.1)
+    for P in (1, 2, 3):
+        N = 200
+        q0, _ = inputs.sod(P, N)
+        pb = oracle.Problem("euler", P, N, bc="transmissive", limiter=True, x_left=0.0, x_right=2.0)
+        r = oracle.run(pb, q0, t_end=0.4, cfl=CFL[P])
+        x = inputs.centers(0.0, 2.0, N, pb.ncells(r.parity), r.parity)
+        W = exact.riemann_sample(WL, WR, (x - 1.0) / 0.4)
+        err = np.abs(r.q[0, 0] - W[0])
+        out[f"P{P}"] = {
+            "N": N, "half_steps": r.half_steps, "parity": r.parity, "t": r.t, "flags": r.flags,
+            "sha256": state_sha(r.q), "L1_rho": float(err.mean()), "Linf_rho": float(err.max()),
+            "contact_L1_rho": region_mean(err, x, *SOD_CONTACT),
+        }
+    return out
+
+
+def titarev_toro():
+    t0 = time.time()
+    Nf = 10000
+    qf, _ = inputs.shu_osher_tt(3, Nf)
+    pbf = oracle.Problem("euler", 3, Nf, bc="transmissive", limiter=True, x_left=-5.0, x_right=5.0)
+    rf = oracle.run(pbf, qf, t_end=5.0, cfl=CFL[3])
+    xf = inputs.centers(-5.0, 5.0, Nf, pbf.ncells(rf.parity), rf.parity)
+    rho_f = rf.q[0, 0]
+    print(f"  fine reference: {rf.half_steps} half-steps, {time.time() - t0:.0f} s", flush=True)
+    out = {"reference": {"P": 3, "N": Nf, "half_steps": rf.half_steps, "parity": rf.parity, "t": rf.t,
+                         "flags": rf.flags, "sha256": state_sha(rf.q),
+                         "rho_f32_b64": base64.b64encode(rho_f.astype("<f4").tobytes()).decode()}}
+    for P in (1, 2, 3):
+        N = 2000
+        q0, _ = inputs.shu_osher_tt(P, N)
+        pb = oracle.Problem("euler", P, N, bc="transmissive", limiter=True, x_left=-5.0, x_right=5.0)
+        r = oracle.run(pb, q0, t_end=5.0, cfl=CFL[P])
+        x = inputs.centers(-5.0, 5.0, N, pb.ncells(r.parity), r.parity)
+        ref = np.interp(x, xf, rho_f)
+        err = np.abs(r.q[0, 0] - ref)
+        out[f"P{P}"] = {
+            "N": N, "half_steps": r.half_steps, "parity": r.parity, "t": r.t, "flags": r.flags,
+            "sha256": state_sha(r.q), "L1_rho": float(err.mean()), "Linf_rho": float(err.max()),
+            "waves_L1_rho": region_mean(err, x, *TT_WAVES),
+        }
+    return out
+
+
+def main():
+    doc = {
+        "_source": "Section 5 of Shen & Parsani (arXiv:2104.04347): Jiang-Shu composite advection (5.1), "
+                   "Sod shock tube and Titarev-Toro modified Shu-Osher problem (5.2); CFL 0.4/0.3/0.25 per "
+                   "half-step for WCCS-2/3/4 (Section 5).  Values computed by the FP64 oracle with "
+                   "tests/golden/write_experiments_1d.py.",
+        "regions": {"jiang_shu": JS_REGIONS, "sod_contact": SOD_CONTACT, "titarev_toro_waves": TT_WAVES},
+    }
+    print("Jiang-Shu ...", flush=True)
+    doc["jiang_shu"] = jiang_shu()
+    print("Sod ...", flush=True)
+    doc["sod"] = sod()
+    print("Titarev-Toro ...", flush=True)
+    doc["titarev_toro"] = titarev_toro()
+    with open(OUT, "w") as f:
+        json.dump(doc, f, indent=1)
+        f.write("\n")
+    print("wrote", OUT)
+
+
+if __name__ == "__main__":
+    main()
