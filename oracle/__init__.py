@@ -42,6 +42,7 @@ class _Problem(ctypes.Structure):
 
 
 _lib = None
+_lib2d = None
 
 
 def _load():
@@ -88,14 +89,14 @@ class use_library:
         self.path = path
 
     def __enter__(self):
-        global _lib, _LIB_PATH
-        self._saved = (_lib, _LIB_PATH)
-        _lib, _LIB_PATH = None, self.path
+        global _lib, _lib2d, _LIB_PATH
+        self._saved = (_lib, _lib2d, _LIB_PATH)
+        _lib, _lib2d, _LIB_PATH = None, None, self.path
         return _load()
 
     def __exit__(self, *exc):
-        global _lib, _LIB_PATH
-        _lib, _LIB_PATH = self._saved
+        global _lib, _lib2d, _LIB_PATH
+        _lib, _lib2d, _LIB_PATH = self._saved
         return False
 
 
@@ -281,3 +282,185 @@ def euler_eigen(gamma: float, U) -> tuple[np.ndarray, np.ndarray]:
     R = np.empty((3, 3))
     lib.wcc_oracle_euler_eigen(float(gamma), _dp(u), _dp(L), _dp(R))
     return L, R
+
+
+# ---------------------------------------------------------------------------
+# 2D half-step (wcc2d_oracle.cpp): Section 3 and Appendix B of the paper on a
+# periodic Cartesian mesh.  State arrays have shape (nc, ndof, Ny, Nx): the
+# DOFs u_{kx,ly} in "DOF order" (total degree k + l ascending, then l
+# ascending), index 0 the point value.
+# ---------------------------------------------------------------------------
+class _Problem2D(ctypes.Structure):
+    _fields_ = [
+        ("equation", ctypes.c_int32),
+        ("P", ctypes.c_int32),
+        ("Nx", ctypes.c_int64),
+        ("Ny", ctypes.c_int64),
+        ("limiter", ctypes.c_int32),
+        ("pad", ctypes.c_int32),
+        ("x_left", ctypes.c_double),
+        ("x_right", ctypes.c_double),
+        ("y_left", ctypes.c_double),
+        ("y_right", ctypes.c_double),
+        ("a", ctypes.c_double),
+        ("b", ctypes.c_double),
+        ("gamma", ctypes.c_double),
+        ("eps", ctypes.c_double),
+    ]
+
+
+def _load2d():
+    global _lib2d
+    if _lib2d is not None:
+        return _lib2d
+    lib = _load()
+    P = ctypes.POINTER
+    dp = P(ctypes.c_double)
+    lib.wcc2d_oracle_old_cell.argtypes = [P(_Problem2D), dp, ctypes.c_double, dp]
+    lib.wcc2d_oracle_old_cell.restype = ctypes.c_int32
+    lib.wcc2d_oracle_js_indicator.argtypes = [ctypes.c_int32, dp]
+    lib.wcc2d_oracle_js_indicator.restype = ctypes.c_double
+    lib.wcc2d_oracle_ndof.argtypes = [ctypes.c_int32]
+    lib.wcc2d_oracle_ndof.restype = ctypes.c_int64
+    lib.wcc2d_oracle_max_speed.argtypes = [P(_Problem2D), dp, P(ctypes.c_int32)]
+    lib.wcc2d_oracle_max_speed.restype = ctypes.c_double
+    lib.wcc2d_oracle_half_step.argtypes = [P(_Problem2D), ctypes.c_int32, dp, ctypes.c_double, dp, dp,
+                                           P(ctypes.c_int32)]
+    lib.wcc2d_oracle_half_step.restype = ctypes.c_int32
+    lib.wcc2d_oracle_run.argtypes = [P(_Problem2D), P(ctypes.c_int32), dp, dp, dp, ctypes.c_double,
+                                     ctypes.c_double, ctypes.c_double, ctypes.c_int64, P(ctypes.c_int32)]
+    lib.wcc2d_oracle_run.restype = ctypes.c_int64
+    _lib2d = lib
+    return lib
+
+
+def ndof2d(P: int) -> int:
+    return (P + 1) * (P + 2) // 2
+
+
+def dof2d(k: int, l: int) -> int:
+    n = k + l
+    return n * (n + 1) // 2 + l
+
+
+@dataclass
+class Problem2D:
+    """u_t + f(u)_x + g(u)_y = 0 on a periodic rectangle (Eq. 2DHCL);
+    advection f = a u, g = b u; Burgers f = g = u^2/2; Euler (rho, rho u,
+    rho v, rho e), unlimited only."""
+    equation: str
+    P: int
+    Nx: int
+    Ny: int
+    limiter: bool = False
+    x_left: float = 0.0
+    x_right: float = 1.0
+    y_left: float = 0.0
+    y_right: float = 1.0
+    a: float = 1.0
+    b: float = 1.0
+    gamma: float = 1.4
+    eps: float = 1e-40
+
+    @property
+    def nc(self) -> int:
+        return 4 if self.equation == "euler" else 1
+
+    @property
+    def nd(self) -> int:
+        return ndof2d(self.P)
+
+    @property
+    def dx(self) -> float:
+        return (self.x_right - self.x_left) / self.Nx
+
+    @property
+    def dy(self) -> float:
+        return (self.y_right - self.y_left) / self.Ny
+
+    @property
+    def shape(self):
+        return (self.nc, self.nd, self.Ny, self.Nx)
+
+    def c_struct(self) -> _Problem2D:
+        s = _Problem2D()
+        s.equation = EQUATIONS[self.equation]
+        s.P, s.Nx, s.Ny = self.P, self.Nx, self.Ny
+        s.limiter = 1 if self.limiter else 0
+        s.x_left, s.x_right, s.y_left, s.y_right = self.x_left, self.x_right, self.y_left, self.y_right
+        s.a, s.b, s.gamma, s.eps = self.a, self.b, self.gamma, self.eps
+        return s
+
+
+def old_cell2d(pb: Problem2D, q: np.ndarray, dt: float) -> dict:
+    """Per-old-cell quantities of one cell (state q of shape (nc, ndof)):
+    quarter-cell averages RU, RD, LU, LD, half-edge flux averages fU, fD, gR,
+    gL (arrays over components) and vertex values V[c][(k, l)], k + l < P."""
+    lib = _load2d()
+    q = np.ascontiguousarray(q, dtype=np.float64)
+    assert q.shape == (pb.nc, pb.nd)
+    nv = pb.P * (pb.P + 1) // 2
+    out = np.zeros(pb.nc * (8 + nv))
+    cs = pb.c_struct()
+    if lib.wcc2d_oracle_old_cell(ctypes.byref(cs), _dp(q), float(dt), _dp(out)) != 0:
+        raise ValueError("oracle rejected the 2D problem")
+    head = out[: 8 * pb.nc].reshape(pb.nc, 8)
+    res = {name: head[:, i].copy() for i, name in enumerate(("RU", "RD", "LU", "LD", "fU", "fD", "gR", "gL"))}
+    pairs = [(n - l, l) for n in range(pb.P) for l in range(n + 1)]
+    tail = out[8 * pb.nc:].reshape(pb.nc, nv)
+    res["V"] = [{kl: tail[c, i] for i, kl in enumerate(pairs)} for c in range(pb.nc)]
+    return res
+
+
+def js_indicator2d(P: int, d: np.ndarray) -> float:
+    """Eq. 2DSmoothIndicator of the polynomial with scaled derivatives d (DOF order)."""
+    d = np.ascontiguousarray(d, dtype=np.float64)
+    assert d.shape == (ndof2d(P),)
+    return _load2d().wcc2d_oracle_js_indicator(int(P), _dp(d))
+
+
+def max_speed2d(pb: Problem2D, q: np.ndarray) -> tuple:
+    """(largest s_x/dx + s_y/dy over the stored averages, status bits)."""
+    lib = _load2d()
+    q = np.ascontiguousarray(q, dtype=np.float64)
+    assert q.shape == pb.shape
+    fl = ctypes.c_int32(0)
+    cs = pb.c_struct()
+    v = lib.wcc2d_oracle_max_speed(ctypes.byref(cs), _dp(q), ctypes.byref(fl))
+    return v, fl.value
+
+
+def half_step2d(pb: Problem2D, parity: int, q: np.ndarray, dt: float):
+    """One half-step from mesh `parity`: (new state, smax of the new averages, flags)."""
+    lib = _load2d()
+    q = np.ascontiguousarray(q, dtype=np.float64)
+    assert q.shape == pb.shape
+    out = np.empty_like(q)
+    sm = ctypes.c_double(0.0)
+    fl = ctypes.c_int32(0)
+    cs = pb.c_struct()
+    rc = lib.wcc2d_oracle_half_step(ctypes.byref(cs), int(parity), _dp(q), float(dt), _dp(out), ctypes.byref(sm),
+                                    ctypes.byref(fl))
+    if rc != 0:
+        raise ValueError("oracle rejected the 2D problem")
+    return out, sm.value, fl.value
+
+
+def run2d(pb: Problem2D, q: np.ndarray, parity: int = 0, t: float = 0.0, t_end: float = float("inf"),
+          cfl: float = 0.0, dt_fixed: float = 0.0, max_half_steps: int = 1 << 62) -> "RunResult":
+    """March 2D half-steps: dt = cfl / smax (smax the largest s_x/dx + s_y/dy),
+    clipped to t_end, or dt_fixed."""
+    lib = _load2d()
+    buf = np.ascontiguousarray(q, dtype=np.float64).copy()
+    assert buf.shape == pb.shape
+    smax, _ = max_speed2d(pb, buf)
+    cp = ctypes.c_int32(parity)
+    ct = ctypes.c_double(t)
+    cs_ = ctypes.c_double(smax)
+    fl = ctypes.c_int32(0)
+    cs = pb.c_struct()
+    taken = lib.wcc2d_oracle_run(ctypes.byref(cs), ctypes.byref(cp), ctypes.byref(ct), ctypes.byref(cs_), _dp(buf),
+                                 float(t_end), float(cfl), float(dt_fixed), int(max_half_steps), ctypes.byref(fl))
+    if taken < 0:
+        raise ValueError("oracle rejected the 2D problem")
+    return RunResult(buf, cp.value, ct.value, cs_.value, int(taken), fl.value)

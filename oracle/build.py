@@ -1,4 +1,4 @@
-"""Build the FP64 CPU oracle (test infrastructure) into oracle/liboracle.so.
+"""Build the FP64 CPU oracle (test infrastructure, 1D and 2D) into oracle/liboracle.so.
 
 Plain g++ with -O2, no contraction and no fast-math, so that every floating
 point operation is the correctly rounded binary64 operation the source names.
@@ -8,7 +8,8 @@ import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SRC = os.path.join(HERE, "wcc_oracle.cpp")
+SRC = os.path.join(HERE, "wcc_oracle.cpp")       # 1D half-step
+SRC2D = os.path.join(HERE, "wcc2d_oracle.cpp")   # 2D half-step
 LIB = os.path.join(HERE, "liboracle.so")
 
 CXXFLAGS = ["-std=c++17", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
@@ -16,7 +17,7 @@ CXXFLAGS = ["-std=c++17", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC",
 
 
 def build(verbose: bool = False) -> str:
-    cmd = ["g++", *CXXFLAGS, "-o", LIB + ".tmp", SRC]
+    cmd = ["g++", *CXXFLAGS, "-o", LIB + ".tmp", SRC, SRC2D]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

@@ -352,3 +352,124 @@ def jiang_shu(P: int, N: int):
     """Projected Jiang-Shu composite on N periodic cells of [-1, 1]."""
     x = centers(-1.0, 1.0, N, N, 0)
     return projected_scalar(jiang_shu_u0, JIANG_SHU_BREAKS, x, 2.0 / N, P)
+
+
+# ---------------------------------------------------------------------------
+# 2D data (Section 3; Table 3's isentropic vortex).  States have shape
+# (nc, ndof, Ny, Nx) with the DOFs u_{kx,ly} = dx^k dy^l d^{k+l}u0/dx^k dy^l
+# at the cell centre in DOF order (k + l ascending, then l ascending).
+# ---------------------------------------------------------------------------
+def ndof2d(P: int) -> int:
+    return (P + 1) * (P + 2) // 2
+
+
+def dof2d(k: int, l: int) -> int:
+    n = k + l
+    return n * (n + 1) // 2 + l
+
+
+def dof_pairs(P: int):
+    """(k, l) in DOF order."""
+    return [(n - l, l) for n in range(P + 1) for l in range(n + 1)]
+
+
+def centers2d(x_left, x_right, y_left, y_right, Nx, Ny, parity):
+    """Cell centres (X, Y), arrays of shape (Ny, Nx); periodic meshes of Nx x Ny
+    cells, the staggered mesh shifted by (dx/2, dy/2)."""
+    x = centers(x_left, x_right, Nx, Nx, parity)
+    y = centers(y_left, y_right, Ny, Ny, parity)
+    return np.meshgrid(x, y)
+
+
+@dataclass
+class Modes2D:
+    """u0 = c0 + sum_m A_m sin(kx_m x + ky_m y + phi_m)."""
+    c0: float
+    amps: np.ndarray
+    kx: np.ndarray
+    ky: np.ndarray
+    phases: np.ndarray
+
+    def deriv(self, X, Y, k: int, l: int):
+        out = np.full_like(X, self.c0 if k + l == 0 else 0.0, dtype=np.float64)
+        for a, wx, wy, ph in zip(self.amps, self.kx, self.ky, self.phases):
+            out = out + a * wx ** k * wy ** l * np.sin(wx * X + wy * Y + ph + (k + l) * np.pi / 2)
+        return out
+
+    def __call__(self, X, Y):
+        return self.deriv(np.asarray(X, dtype=np.float64), np.asarray(Y, dtype=np.float64), 0, 0)
+
+
+def taylor2d(fn: Modes2D, P: int, Nx: int, Ny: int, domain=(0.0, 2.0, 0.0, 2.0), parity: int = 0):
+    x0, x1, y0, y1 = domain
+    X, Y = centers2d(x0, x1, y0, y1, Nx, Ny, parity)
+    dx, dy = (x1 - x0) / Nx, (y1 - y0) / Ny
+    q = np.empty((1, ndof2d(P), Ny, Nx))
+    for k, l in dof_pairs(P):
+        q[0, dof2d(k, l)] = dx ** k * dy ** l * fn.deriv(X, Y, k, l)
+    return q
+
+
+def modes2d(seed: int, n_modes: int = 3, c0: float = 0.5, amp: float = 0.5, kmax: int = 3) -> Modes2D:
+    """Seeded sum of sine modes periodic on [0, 2]^2: A ~ U(0, amp/n_modes),
+    integer wavenumbers in [-kmax, kmax] (times pi), not both zero."""
+    rng = np.random.default_rng(seed)
+    kx, ky = [], []
+    while len(kx) < n_modes:
+        a, b = rng.integers(-kmax, kmax + 1, 2)
+        if a or b:
+            kx.append(a)
+            ky.append(b)
+    amps = rng.uniform(0.0, amp / n_modes, n_modes)
+    phases = rng.uniform(0.0, 2 * np.pi, n_modes)
+    return Modes2D(c0, amps, np.pi * np.array(kx, float), np.pi * np.array(ky, float), phases)
+
+
+_VORTEX_CACHE: dict = {}
+
+
+def _vortex_functions(P: int, gamma: float, psi: float):
+    """Numerical functions d^{k+l}/dx^k dy^l of (rho, rho u, rho v, rho e) of
+    the isentropic vortex (Section 5.3.1), from symbolic differentiation."""
+    key = (P, gamma, psi)
+    if key in _VORTEX_CACHE:
+        return _VORTEX_CACHE[key]
+    import sympy as sp
+    x, y = sp.symbols("x y", real=True)
+    g = sp.Rational(gamma).limit_denominator(1000) if isinstance(gamma, float) else gamma
+    ps = sp.nsimplify(psi)
+    e = sp.exp(sp.Rational(1, 2) * (1 - x * x - y * y))
+    du, dv = ps / (2 * sp.pi) * e * (-y), ps / (2 * sp.pi) * e * x
+    T = 1 - (g - 1) * ps ** 2 / (8 * g * sp.pi ** 2) * e ** 2
+    rho = T ** (1 / (g - 1))
+    p = rho * T
+    u, v = 1 + du, 1 + dv
+    U = [rho, rho * u, rho * v, p / (g - 1) + rho * (u * u + v * v) / 2]
+    fns = {}
+    for k, l in dof_pairs(P):
+        fns[(k, l)] = [sp.lambdify((x, y), sp.diff(c, x, k, y, l) if k + l else c, "numpy") for c in U]
+    _VORTEX_CACHE[key] = fns
+    return fns
+
+
+def vortex_state(X, Y, t: float = 0.0, gamma: float = 1.4, psi: float = 5.0, L: float = 10.0):
+    """Conserved (rho, rho u, rho v, rho e) of the vortex moved by (t, t), the
+    position wrapped into the periodic box [-L/2, L/2]^2 (the exact solution)."""
+    fns = _vortex_functions(0, gamma, psi)[(0, 0)]
+    xs = (X - t + L / 2) % L - L / 2
+    ys = (Y - t + L / 2) % L - L / 2
+    return np.stack([np.broadcast_to(f(xs, ys), X.shape) for f in fns])
+
+
+def isentropic_vortex(P: int, N: int, parity: int = 0, gamma: float = 1.4, psi: float = 5.0):
+    """Taylor data of the isentropic vortex on the periodic [-5, 5]^2 with
+    N x N cells (Section 5.3.1): uniform rho = 1, p = 1, (u, v) = (1, 1) plus
+    the isentropic perturbation of strength psi."""
+    X, Y = centers2d(-5.0, 5.0, -5.0, 5.0, N, N, parity)
+    h = 10.0 / N
+    fns = _vortex_functions(P, gamma, psi)
+    q = np.empty((4, ndof2d(P), N, N))
+    for k, l in dof_pairs(P):
+        for c in range(4):
+            q[c, dof2d(k, l)] = h ** (k + l) * np.broadcast_to(fns[(k, l)][c](X, Y), X.shape)
+    return q
