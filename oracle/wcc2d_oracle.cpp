@@ -32,7 +32,8 @@
 // contraction; sums of products left to right as s = c0*x0; s = fma(ci, xi, s);
 // constants exact rationals rounded once).  Index order of every sum: over
 // (k, l) pairs by total degree n = k + l ascending, then l ascending (the
-// "DOF order"); over (a, b, c) in Taylor products a outer, b, c inner.
+// "DOF order"); over (a, b, c) in Taylor products a outer, b, c inner; the
+// half-edge flux averages time index outer, offset inner (Appendix B).
 //
 // Readings (design notes of the repository): state = point value; time step
 // dt = cfl / max_cells(s_x/dx + s_y/dy) from the cell averages, recomputed
@@ -221,11 +222,11 @@ void old_cell(const wcc2d_oracle_problem& pb, const double q[NCMAX][32], const d
       }
     o.RU[c] = ru; o.RD[c] = rd; o.LU[c] = lu; o.LD[c] = ld;
     // half-edge flux averages: f along the line x = x_i (y offset s, time m),
-    // g along y = y_j (x offset s, time m); pairs (s, m) in DOF order
+    // g along y = y_j (x offset s, time m); time index outer, offset inner,
+    // the order of the double sums of Appendix B
     double fu = F[c][0][0][0], fd = F[c][0][0][0], gr = G[c][0][0][0], gl = G[c][0][0][0];
-    for (int n = 1; n <= P; ++n)
-      for (int m = 0; m <= n; ++m) {
-        const int s = n - m;
+    for (int m = 0; m <= P; ++m)
+      for (int s = (m == 0) ? 1 : 0; s <= P - m; ++s) {
         const double fi = K.FI[s][m];
         fu = std::fma(fi, F[c][0][s][m], fu);
         fd = std::fma((s % 2) ? -fi : fi, F[c][0][s][m], fd);
