@@ -48,6 +48,23 @@ class wcc_state_info(ctypes.Structure):
     ]
 
 
+class wcc2d_params(ctypes.Structure):
+    _fields_ = [
+        ("x_left", ctypes.c_double), ("x_right", ctypes.c_double),
+        ("y_left", ctypes.c_double), ("y_right", ctypes.c_double),
+        ("a", ctypes.c_double), ("b", ctypes.c_double), ("gamma", ctypes.c_double), ("eps", ctypes.c_double),
+        ("limiter", ctypes.c_int32), ("reserved", ctypes.c_int32),
+    ]
+
+
+class wcc2d_state_info(ctypes.Structure):
+    _fields_ = [
+        ("t", ctypes.c_double), ("parity", ctypes.c_int32), ("flags", ctypes.c_int32),
+        ("Nx", ctypes.c_int64), ("Ny", ctypes.c_int64), ("dx", ctypes.c_double), ("dy", ctypes.c_double),
+        ("half_steps", ctypes.c_int64), ("s_max", ctypes.c_double),
+    ]
+
+
 _c = ctypes
 _vp, _i64, _dp = _c.c_void_p, _c.c_int64, _c.POINTER(_c.c_double)
 SIGNATURES = {
@@ -78,6 +95,19 @@ SIGNATURES = {
     "wcc_batch_last_run_ms": ([_vp, _dp], _c.c_int),
     "wcc_batch_last_error": ([_vp], _c.c_char_p),
     "wcc_batch_destroy": ([_vp], None),
+    "wcc2d_params_default": ([_c.POINTER(wcc2d_params)], _c.c_int),
+    "wcc2d_create": ([_c.c_int, _c.c_int, _i64, _i64, _c.POINTER(wcc2d_params), _c.POINTER(_vp)], _c.c_int),
+    "wcc2d_workspace_bytes": ([_vp, _c.POINTER(_c.c_size_t)], _c.c_int),
+    "wcc2d_bind": ([_vp, _vp, _c.c_size_t, _vp], _c.c_int),
+    "wcc2d_write_dofs": ([_vp, _dp, _c.c_int, _c.c_double], _c.c_int),
+    "wcc2d_step": ([_vp, _c.c_double, _c.c_double], _c.c_int),
+    "wcc2d_run": ([_vp, _i64, _c.c_double], _c.c_int),
+    "wcc2d_advance": ([_vp, _c.c_double, _c.c_double, _i64, _c.POINTER(_i64)], _c.c_int),
+    "wcc2d_read_dofs": ([_vp, _dp, _i64, _c.POINTER(wcc2d_state_info)], _c.c_int),
+    "wcc2d_set_launch": ([_vp, _c.c_int, _c.c_int], _c.c_int),
+    "wcc2d_last_run_ms": ([_vp, _dp], _c.c_int),
+    "wcc2d_last_error": ([_vp], _c.c_char_p),
+    "wcc2d_destroy": ([_vp], None),
 }
 
 _lib = None
@@ -107,12 +137,13 @@ def _dptr(a: np.ndarray):
     return a.ctypes.data_as(_dp)
 
 
-def _check(rc: int, what: str, ctx=None, batch=False):
+def _check(rc: int, what: str, ctx=None, batch=False, two_d=False):
     if rc != WCC_OK:
         lib = load()
         detail = ""
         if ctx is not None:
-            detail = (lib.wcc_batch_last_error(ctx) if batch else lib.wcc_last_error(ctx)) or b""
+            err = lib.wcc2d_last_error if two_d else (lib.wcc_batch_last_error if batch else lib.wcc_last_error)
+            detail = err(ctx) or b""
             detail = detail.decode(errors="replace")
         raise WccError(rc, f"{what}: {lib.wcc_strerror(rc).decode()}" + (f" -- {detail}" if detail else ""))
 
@@ -299,6 +330,90 @@ class Batch:
     def close(self):
         if getattr(self, "h", None):
             load().wcc_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+DOF2D_NOTE = "DOF order: k + l ascending, then l ascending; index (k+l)(k+l+1)/2 + l"
+
+
+class Solver2D:
+    """One 2D instance on a periodic rectangle: u_t + f(u)_x + g(u)_y = 0
+    advanced by the gfx950 2D half-step kernel.  States are numpy arrays of
+    shape (nc, ndof, Ny, Nx) in DOF order."""
+
+    def __init__(self, equation: str, P: int, Nx: int, Ny: int, *, limiter: bool = True, x_left: float = 0.0,
+                 x_right: float = 1.0, y_left: float = 0.0, y_right: float = 1.0, a: float = 1.0, b: float = 1.0,
+                 gamma: float = 1.4, eps: float = 1e-40, stream=None):
+        lib = load()
+        self.equation, self.P, self.Nx, self.Ny = equation, P, Nx, Ny
+        self.nc = 4 if equation == "euler" else 1
+        self.nd = (P + 1) * (P + 2) // 2
+        p = wcc2d_params()
+        lib.wcc2d_params_default(ctypes.byref(p))
+        p.x_left, p.x_right, p.y_left, p.y_right = x_left, x_right, y_left, y_right
+        p.a, p.b, p.gamma, p.eps = a, b, gamma, eps
+        p.limiter = 1 if limiter else 0
+        self.params = p
+        h = ctypes.c_void_p()
+        _check(lib.wcc2d_create(EQUATIONS[equation], P, Nx, Ny, ctypes.byref(p), ctypes.byref(h)), "wcc2d_create")
+        self.h = h
+        nb = ctypes.c_size_t()
+        _check(lib.wcc2d_workspace_bytes(h, ctypes.byref(nb)), "wcc2d_workspace_bytes", h, two_d=True)
+        self.workspace = _torch_device_buffer(nb.value)
+        self.stream = stream if stream is not None else _torch_stream_handle()
+        _check(lib.wcc2d_bind(h, ctypes.c_void_p(self.workspace.data_ptr()), nb.value, ctypes.c_void_p(self.stream)),
+               "wcc2d_bind", h, two_d=True)
+
+    @property
+    def shape(self):
+        return (self.nc, self.nd, self.Ny, self.Nx)
+
+    def write(self, q: np.ndarray, parity: int = 0, t: float = 0.0) -> None:
+        q = np.ascontiguousarray(q, dtype=np.float64)
+        assert q.shape == self.shape, (q.shape, self.shape)
+        _check(load().wcc2d_write_dofs(self.h, _dptr(q), parity, float(t)), "wcc2d_write_dofs", self.h, two_d=True)
+
+    def step(self, cfl: float = 0.0, dt_fixed: float = 0.0) -> None:
+        _check(load().wcc2d_step(self.h, float(cfl), float(dt_fixed)), "wcc2d_step", self.h, two_d=True)
+
+    def run(self, half_steps: int, cfl: float) -> None:
+        _check(load().wcc2d_run(self.h, int(half_steps), float(cfl)), "wcc2d_run", self.h, two_d=True)
+
+    def advance(self, t_end: float, cfl: float, max_half_steps: int = 0) -> int:
+        taken = ctypes.c_int64()
+        _check(load().wcc2d_advance(self.h, float(t_end), float(cfl), int(max_half_steps), ctypes.byref(taken)),
+               "wcc2d_advance", self.h, two_d=True)
+        return taken.value
+
+    def info(self) -> wcc2d_state_info:
+        inf = wcc2d_state_info()
+        _check(load().wcc2d_read_dofs(self.h, None, 0, ctypes.byref(inf)), "wcc2d_read_dofs", self.h, two_d=True)
+        return inf
+
+    def read(self):
+        q = np.empty(self.shape, dtype=np.float64)
+        inf = wcc2d_state_info()
+        _check(load().wcc2d_read_dofs(self.h, _dptr(q), q.size, ctypes.byref(inf)), "wcc2d_read_dofs", self.h,
+               two_d=True)
+        return q, inf
+
+    def set_launch(self, threads: int = 0, blocks: int = 0) -> None:
+        _check(load().wcc2d_set_launch(self.h, int(threads), int(blocks)), "wcc2d_set_launch", self.h, two_d=True)
+
+    def last_run_ms(self) -> float:
+        ms = ctypes.c_double()
+        _check(load().wcc2d_last_run_ms(self.h, ctypes.byref(ms)), "wcc2d_last_run_ms", self.h, two_d=True)
+        return ms.value
+
+    def close(self) -> None:
+        if getattr(self, "h", None):
+            load().wcc2d_destroy(self.h)
             self.h = None
 
     def __del__(self):

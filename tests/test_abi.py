@@ -1,5 +1,6 @@
 """CPU checks of the boundary: the HIP library loads, exports every symbol that
-include/wcc.h declares, and validates arguments in the calls that need no GPU."""
+include/wcc.h and include/wcc2d.h declare, and validates arguments in the
+calls that need no GPU."""
 import ctypes
 import os
 import re
@@ -9,17 +10,17 @@ import pytest
 from paper_2104_04347_amd import binding
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "wcc.h")
+HEADERS = [os.path.join(ROOT, "include", h) for h in ("wcc.h", "wcc2d.h")]
 
 
 def declared():
-    txt = open(HEADER).read()
-    return sorted(set(re.findall(r"^(?:int|void|const char\*)\s+(wcc_\w+)\s*\(", txt, re.M)))
+    txt = "".join(open(h).read() for h in HEADERS)
+    return sorted(set(re.findall(r"^(?:int|void|const char\*)\s+(wcc(?:2d)?_\w+)\s*\(", txt, re.M)))
 
 
 def test_header_declares_the_abi():
     names = declared()
-    assert "wcc_create" in names and "wcc_batch_run" in names and len(names) >= 20
+    assert "wcc_create" in names and "wcc_batch_run" in names and "wcc2d_advance" in names and len(names) >= 33
 
 
 def test_library_exports_every_declared_symbol():
@@ -93,3 +94,25 @@ def test_product_path_has_no_cpu_fallback(monkeypatch):
     monkeypatch.setattr(binding, "_lib", None)
     with pytest.raises(RuntimeError):
         binding.load("/nonexistent/libwcc.so")
+
+
+def test_2d_create_validates():
+    lib = binding.load()
+    h = ctypes.c_void_p()
+    p = binding.wcc2d_params()
+    assert lib.wcc2d_params_default(ctypes.byref(p)) == 0
+    assert p.limiter == 1 and p.eps == 1e-40 and p.x_right == 1.0 and p.b == 1.0
+    for eq, P, nx, ny in [(3, 2, 64, 64), (0, 4, 64, 64), (0, -1, 64, 64), (0, 2, 1, 64), (0, 2, 1 << 15, 1 << 14)]:
+        assert lib.wcc2d_create(eq, P, nx, ny, ctypes.byref(p), ctypes.byref(h)) == binding.WCC_EINVAL
+    # Euler: the limiter is not available in 2D (unlimited form only)
+    assert lib.wcc2d_create(2, 2, 64, 64, ctypes.byref(p), ctypes.byref(h)) == binding.WCC_EINVAL
+    p.limiter = 0
+    assert lib.wcc2d_create(2, 3, 100, 50, ctypes.byref(p), ctypes.byref(h)) == 0
+    nb = ctypes.c_size_t()
+    assert lib.wcc2d_workspace_bytes(h, ctypes.byref(nb)) == 0
+    plane = (100 * 50 + 63) // 64 * 64
+    assert nb.value >= 2 * 4 * 10 * plane * 8            # two buffers of 4 components x 10 DOFs
+    assert lib.wcc2d_step(h, ctypes.c_double(0.25), ctypes.c_double(0.0)) == binding.WCC_ESTATE
+    assert lib.wcc2d_bind(h, ctypes.c_void_p(256), 16, None) == binding.WCC_ESIZE
+    assert lib.wcc2d_set_launch(h, 100, 0) == binding.WCC_EINVAL
+    lib.wcc2d_destroy(h)

@@ -1,0 +1,120 @@
+"""GPU parity of the 2D half-step (Section 3, Appendix B; unlimited 2D Euler)
+against the 2D oracle: bit for bit (binary64, the same written operation
+order on both sides), on ragged tile edges, meshes narrower than a tile,
+graph-replayed runs and the Euler vortex of Table 3."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2104_04347_amd import binding, inputs
+
+pytestmark = pytest.mark.gpu
+CFL = {0: 0.4, 1: 0.4, 2: 0.3, 3: 0.25}
+
+
+def gpu_run(eq, P, Nx, Ny, q0, limiter, dom=(0.0, 2.0, 0.0, 2.0), cfl=None, half_steps=None, t_end=None, a=0.7,
+            b=-0.4, dt_fixed=None):
+    s = binding.Solver2D(eq, P, Nx, Ny, limiter=limiter, x_left=dom[0], x_right=dom[1], y_left=dom[2],
+                         y_right=dom[3], a=a, b=b)
+    try:
+        s.write(q0)
+        if dt_fixed is not None:
+            for _ in range(half_steps):
+                s.step(dt_fixed=dt_fixed)
+        elif t_end is not None:
+            s.advance(t_end, cfl)
+        else:
+            s.run(half_steps, cfl)
+        q, info = s.read()
+    finally:
+        s.close()
+    return q, info
+
+
+def oracle_run(eq, P, Nx, Ny, q0, limiter, dom=(0.0, 2.0, 0.0, 2.0), cfl=0.0, half_steps=1 << 62, t_end=np.inf,
+               a=0.7, b=-0.4, dt_fixed=0.0):
+    pb = oracle.Problem2D(eq, P, Nx, Ny, limiter=limiter, x_left=dom[0], x_right=dom[1], y_left=dom[2],
+                          y_right=dom[3], a=a, b=b)
+    return oracle.run2d(pb, q0, cfl=cfl, t_end=t_end, dt_fixed=dt_fixed, max_half_steps=half_steps)
+
+
+def assert_bitwise(q, info, r, label):
+    print(label, flush=True)
+    assert info.flags & 3 == 0 and r.flags == 0, (label, info.flags, r.flags)
+    assert info.parity == r.parity and info.t == r.t, (label, info.t, r.t)
+    bad = np.argwhere(q.view(np.uint64) != r.q.view(np.uint64))
+    assert bad.size == 0, (label, bad[:5], q[tuple(bad[0])], r.q[tuple(bad[0])])
+
+
+def modes_state(P, Nx, Ny, seed=3):
+    fn = inputs.modes2d(seed)
+    return inputs.taylor2d(fn, P, Nx, Ny)
+
+
+@pytest.mark.parametrize("eq", ["advection", "burgers"])
+@pytest.mark.parametrize("P", [0, 1, 2, 3])
+@pytest.mark.parametrize("limiter", [False, True])
+def test_scalar_bitwise(eq, P, limiter):
+    Nx, Ny = 37, 29                       # ragged 7-cell tiles in both directions
+    q0 = modes_state(P, Nx, Ny)
+    q, info = gpu_run(eq, P, Nx, Ny, q0, limiter, cfl=CFL[P], half_steps=30)
+    r = oracle_run(eq, P, Nx, Ny, q0, limiter, cfl=CFL[P], half_steps=30)
+    assert_bitwise(q, info, r, f"{eq} P={P} lim={limiter}")
+
+
+@pytest.mark.parametrize("Nx,Ny", [(2, 3), (5, 7), (8, 8), (9, 2), (15, 14)])
+def test_small_meshes_bitwise(Nx, Ny):
+    P = 3
+    q0 = modes_state(P, Nx, Ny, seed=4)
+    q, info = gpu_run("burgers", P, Nx, Ny, q0, True, cfl=CFL[P], half_steps=9)
+    r = oracle_run("burgers", P, Nx, Ny, q0, True, cfl=CFL[P], half_steps=9)
+    assert_bitwise(q, info, r, f"Nx={Nx} Ny={Ny}")
+
+
+def test_graph_replay_and_advance_bitwise():
+    """A run of 2 x 48 + 5 half-steps (graph chunks and single launches),
+    then an advance to a time that clips the last step."""
+    P, Nx, Ny = 2, 50, 43
+    q0 = modes_state(P, Nx, Ny, seed=5)
+    q, info = gpu_run("burgers", P, Nx, Ny, q0, True, cfl=CFL[P], half_steps=101)
+    r = oracle_run("burgers", P, Nx, Ny, q0, True, cfl=CFL[P], half_steps=101)
+    assert_bitwise(q, info, r, "run 101")
+    q, info = gpu_run("burgers", P, Nx, Ny, q0, True, cfl=CFL[P], t_end=0.123)
+    r = oracle_run("burgers", P, Nx, Ny, q0, True, cfl=CFL[P], t_end=0.123)
+    assert info.t == 0.123
+    assert_bitwise(q, info, r, "advance 0.123")
+
+
+def test_fixed_dt_bitwise():
+    P, Nx, Ny = 3, 21, 22
+    q0 = modes_state(P, Nx, Ny, seed=6)
+    dt = 0.01
+    q, info = gpu_run("advection", P, Nx, Ny, q0, True, half_steps=5, dt_fixed=dt)
+    r = oracle_run("advection", P, Nx, Ny, q0, True, half_steps=5, dt_fixed=dt)
+    assert_bitwise(q, info, r, "fixed dt")
+
+
+@pytest.mark.parametrize("P", [1, 2, 3])
+def test_euler_vortex_bitwise(P):
+    """Table 3's setup (isentropic vortex, mesh 1/5, t = 2), unlimited."""
+    N = 50
+    q0 = inputs.isentropic_vortex(P, N)
+    dom = (-5.0, 5.0, -5.0, 5.0)
+    q, info = gpu_run("euler", P, N, N, q0, False, dom=dom, cfl=CFL[P], t_end=2.0)
+    r = oracle_run("euler", P, N, N, q0, False, dom=dom, cfl=CFL[P], t_end=2.0)
+    assert_bitwise(q, info, r, f"vortex P={P}")
+
+
+def test_2d_errors():
+    s = binding.Solver2D("burgers", 2, 16, 16)
+    with pytest.raises(binding.WccError):
+        s.step(cfl=0.25)                      # no state written
+    q0 = modes_state(2, 16, 16)
+    s.write(q0)
+    with pytest.raises(binding.WccError):
+        s.run(10, 1.5)                        # cfl outside (0, 1]
+    bad = q0.copy()
+    bad[0, 0, 3, 4] = np.nan
+    with pytest.raises(binding.WccError):
+        s.write(bad)
+    s.close()
