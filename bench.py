@@ -167,6 +167,55 @@ def time_batch(args):
                 schedule=sched or "default")
 
 
+def time_2d(args):
+    """The 2D half-step (Section 3): Burgers with the limiter, P = 3, on a
+    2048 x 2048 periodic mesh of [0, 2]^2 with seeded sine modes; and the
+    unlimited Euler isentropic vortex of Table 3, P = 3, 1024 x 1024 on
+    [-5, 5]^2.  Binary64.  Algorithmic bytes per launch: every old cell read
+    once and every new cell written once, nc * ndof doubles each."""
+    import torch
+    from paper_2104_04347_amd import binding, inputs
+    out = {}
+    cases = [("burgers_lim_P3", "burgers", 3, args.n2d, True, (0.0, 2.0, 0.0, 2.0), 0.25,
+              lambda: inputs.taylor2d(inputs.modes2d(args.seed), 3, args.n2d, args.n2d)),
+             ("euler_vortex_P3", "euler", 3, args.n2d_euler, False, (-5.0, 5.0, -5.0, 5.0), 0.25,
+              lambda: inputs.isentropic_vortex(3, args.n2d_euler))]
+    for name, eq, P, N, lim, dom, cfl, make in cases:
+        q0 = make()
+        s = binding.Solver2D(eq, P, N, N, limiter=lim, x_left=dom[0], x_right=dom[1], y_left=dom[2], y_right=dom[3])
+        s.write(q0)
+        s.run(args.warmup2d, cfl)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.run(args.steps2d, cfl)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        launch_s = s.last_run_ms() / 1e3 / args.steps2d
+        info = s.info()
+        nc, nd = s.nc, s.nd
+        dofs = N * N * nc * nd * args.steps2d
+        bpl = 2.0 * N * N * nc * nd * 8
+        e = {"value": dofs / wall, "unit": "cell-DOF updates/s", "N": N, "P": P, "limiter": lim,
+             "cfl": cfl, "half_steps": args.steps2d, "launch_us": launch_s * 1e6, "bytes_per_launch": bpl,
+             "hbm_frac": bpl / launch_s / HBM_PEAK, "valid": bool((info.flags & 3) == 0)}
+        s.close()
+        if not args.no_cpu:
+            import oracle
+            pb = oracle.Problem2D(eq, P, N, N, limiter=lim, x_left=dom[0], x_right=dom[1], y_left=dom[2],
+                                  y_right=dom[3])
+            t0 = time.perf_counter()
+            r = oracle.run2d(pb, q0, cfl=cfl, max_half_steps=1)
+            cw = time.perf_counter() - t0
+            e["cpu_baseline"] = {"value": N * N * nc * nd * r.half_steps / cw, "unit": "cell-DOF updates/s",
+                                 "cores": 1, "kind": "oracle",
+                                 "sample": f"first half-step of the same workload, FP64 oracle, single thread, "
+                                           f"{cw:.1f} s"}
+        out[name] = e
+        del q0
+        print(f"[bench] 2D {name}: {e['value']:.3e} DOF/s", file=sys.stderr, flush=True)
+    return out
+
+
 def cpu_baseline_batch(args):
     """The FP64 oracle, single-threaded, on one half-step of every instance of
     the batched workload (the cost of a half-step does not depend on which one
@@ -279,6 +328,11 @@ def main():
     ap.add_argument("--batch-schedule", default="", help="threads,blocks,mode for the batched kernels")
     ap.add_argument("--cpu-steps", type=int, default=24)
     ap.add_argument("--large-cpu-steps", type=int, default=5, help="oracle half-steps timed on the large workload")
+    ap.add_argument("--no-2d", action="store_true", help="skip the 2D legs")
+    ap.add_argument("--n2d", type=int, default=2048, help="2D Burgers mesh (n2d x n2d)")
+    ap.add_argument("--n2d-euler", type=int, default=1024, help="2D Euler vortex mesh")
+    ap.add_argument("--steps2d", type=int, default=240)
+    ap.add_argument("--warmup2d", type=int, default=96)
     ap.add_argument("--seeds", default="0,1,2,3,4",
                     help="also time the FP64 and mixed legs on these seeds of the same workload ('' for none)")
     ap.add_argument("--large", action="store_true", help="also run the large 16.7M-cell P=4 workload")
@@ -327,6 +381,14 @@ def main():
     if not args.no_batch:
         rb = time_batch(args)
         print(f"[bench] batched: {rb['value']:.1f} solves/s", file=sys.stderr, flush=True)
+
+    r2 = None
+    if not args.no_2d:
+        try:
+            r2 = time_2d(args)
+        except Exception as exc:          # reported, never hides the 1D line
+            r2 = {"error": f"{type(exc).__name__}: {exc}"}
+            print(f"[bench] 2D legs failed: {exc}", file=sys.stderr, flush=True)
 
     rl = None
     if args.large:
@@ -403,6 +465,8 @@ def main():
                               "launch": rmx["launch"]}
     if rb is not None:
         line["batched"] = rb
+    if r2 is not None:
+        line["two_d"] = r2
     if rl is not None:
         line["large"] = rl
     if seeds_out:
