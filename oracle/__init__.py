@@ -347,7 +347,8 @@ def dof2d(k: int, l: int) -> int:
 class Problem2D:
     """u_t + f(u)_x + g(u)_y = 0 on a periodic rectangle (Eq. 2DHCL);
     advection f = a u, g = b u; Burgers f = g = u^2/2; Euler (rho, rho u,
-    rho v, rho e), unlimited only."""
+    rho v, rho e), limited in the characteristic fields of the rotated
+    decomposition (Section 4)."""
     equation: str
     P: int
     Nx: int

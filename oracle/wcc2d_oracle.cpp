@@ -22,10 +22,11 @@
 //     derivatives, highest total order first, x-formula (Eq. SubEq:2DUx),
 //     y-formula (Eq. SubEq:2DUy), cross derivatives as the mean of the two
 //     (the remark after Eq. 2DDerivatives);
-//   * scalar equations: the 2D limiter of Section 3.2 (five candidates,
-//     Eq. 2DLimitedPolynomial, 2DLowOrderPolynomial, 2D2ndOrderWeights for
-//     P = 1, the high-order weights with sigma and tau for P >= 2, smoothness
-//     indicator Eq. 2DSmoothIndicator);
+//   * the 2D limiter of Section 3.2 (five candidates, Eq.
+//     2DLimitedPolynomial, 2DLowOrderPolynomial, 2D2ndOrderWeights for P = 1,
+//     the high-order weights with sigma and tau for P >= 2, smoothness
+//     indicator Eq. 2DSmoothIndicator); for the Euler equations applied to
+//     the characteristic fields of the rotated decomposition of Section 4;
 //   * new point value from the new average (inverse of Eq. SubEq:2DCellAVG).
 //
 // Canonical arithmetic: the rules of the 1D oracle (binary64, no
@@ -348,6 +349,83 @@ void limit2d(int P, double eps, double abar, double D[PMAX + 1][PMAX + 1], doubl
     for (int l = 0; l <= n; ++l) D[n - l][l] = w[0] * D[n - l][l];
 }
 
+// Rotated characteristic limiting of a 2D Euler new cell (Section 4):
+// direction n = grad(phi)/|grad(phi)| with phi = rho e (Section 5.3) from the
+// new cell's central-difference derivatives (Eq. RotatedNormal; n = (1, 0)
+// where the gradient vanishes); left/right eigenvectors of
+// A cos(theta) + B sin(theta) at the new average; every candidate of
+// Eq. 2DLowOrderPolynomial / 2DHighOrderPolynomial projected with L, each
+// characteristic field limited by limit2d, the result projected back with R.
+// ab: conserved average; D[c]: unlimited derivatives (modified in place);
+// v[c][vtx]: vertex values, vtx = LD, RD, RU, LU.
+void char_limit2d(int P, double gamma, double eps, double dx, double dy, const double ab[4],
+                  double D[4][PMAX + 1][PMAX + 1], const double v[4][4]) {
+  const double gx = D[3][1][0] / dx, gy = D[3][0][1] / dy;
+  const double g2 = std::fma(gy, gy, gx * gx);
+  double nx = 1.0, ny = 0.0;
+  if (g2 > 0.0) {
+    const double gn = std::sqrt(g2);
+    nx = gx / gn;
+    ny = gy / gn;
+  }
+  const double rho = ab[0], u = ab[1] / rho, vv = ab[2] / rho;
+  const double p = (gamma - 1.0) * (ab[3] - 0.5 * std::fma(ab[2], vv, ab[1] * u));
+  const double c = std::sqrt((gamma * p) / rho);
+  const double H = (ab[3] + p) / rho;
+  const double un = std::fma(vv, ny, u * nx), ut = std::fma(vv, nx, -(u * ny));
+  const double q2 = std::fma(vv, vv, u * u);
+  const double ic = 1.0 / c;
+  const double b1 = (gamma - 1.0) * (ic * ic), b2 = 0.5 * (q2 * b1);
+  const double uic = un * ic, nxic = nx * ic, nyic = ny * ic, b1u = b1 * u, b1v = b1 * vv;
+  // rows of L; the third row has no energy entry
+  const double L[4][4] = {{0.5 * (b2 + uic), -0.5 * (b1u + nxic), -0.5 * (b1v + nyic), 0.5 * b1},
+                          {1.0 - b2, b1u, b1v, -b1},
+                          {-ut, -ny, nx, 0.0},
+                          {0.5 * (b2 - uic), -0.5 * (b1u - nxic), -0.5 * (b1v - nyic), 0.5 * b1}};
+  // columns of R; the third column has no density entry
+  const double cun = c * un;
+  const double R[4][4] = {{1.0, u - c * nx, vv - c * ny, H - cun},
+                          {1.0, u, vv, 0.5 * q2},
+                          {0.0, -ny, nx, ut},
+                          {1.0, u + c * nx, vv + c * ny, H + cun}};
+  auto proj = [&](int f, const double x[4]) {
+    double s = L[f][0] * x[0];
+    s = std::fma(L[f][1], x[1], s);
+    s = std::fma(L[f][2], x[2], s);
+    if (f != 2) s = std::fma(L[f][3], x[3], s);
+    return s;
+  };
+  double out[4][PMAX + 1][PMAX + 1] = {};
+  for (int f = 0; f < 4; ++f) {
+    double x[4];
+    for (int r = 0; r < 4; ++r) x[r] = ab[r];
+    const double ca = proj(f, x);
+    double cv[4];
+    for (int vtx = 0; vtx < 4; ++vtx) {
+      for (int r = 0; r < 4; ++r) x[r] = v[r][vtx];
+      cv[vtx] = proj(f, x);
+    }
+    double cD[PMAX + 1][PMAX + 1] = {};
+    for (int n = 1; n <= P; ++n)
+      for (int l = 0; l <= n; ++l) {
+        for (int r = 0; r < 4; ++r) x[r] = D[r][n - l][l];
+        cD[n - l][l] = proj(f, x);
+      }
+    limit2d(P, eps, ca, cD, cv[0], cv[1], cv[2], cv[3]);
+    for (int r = 0; r < 4; ++r) {
+      if (f == 2 && r == 0) continue;
+      for (int n = 1; n <= P; ++n)
+        for (int l = 0; l <= n; ++l) {
+          const int k = n - l;
+          out[r][k][l] = (f == 0) ? R[f][r] * cD[k][l] : std::fma(R[f][r], cD[k][l], out[r][k][l]);
+        }
+    }
+  }
+  for (int r = 0; r < 4; ++r)
+    for (int n = 1; n <= P; ++n)
+      for (int l = 0; l <= n; ++l) D[r][n - l][l] = out[r][n - l][l];
+}
+
 struct Mesh {
   int64_t Nx, Ny;
   int64_t wrapx(int64_t i) const { return (i % Nx + Nx) % Nx; }
@@ -424,6 +502,7 @@ void half_step(const wcc2d_oracle_problem& pb, int parity, const double* qin, do
       const Old& C = old[(size_t)(j0 * pb.Nx + i1)];   // lower-right
       const Old& Dd = old[(size_t)(j1 * pb.Nx + i1)];  // upper-right
       double ab[NCMAX];
+      double D[NCMAX][PMAX + 1][PMAX + 1] = {};
       for (int c = 0; c < nc; ++c) {
         // Eq. 2DIntegral; the flux terms are grouped as differences of the
         // same half-edge flux on opposite faces, so that data uniform in the
@@ -431,10 +510,8 @@ void half_step(const wcc2d_oracle_problem& pb, int parity, const double* qin, do
         const double h = 0.25 * (((A.RU[c] + B.RD[c]) + C.LU[c]) + Dd.LD[c]);
         const double fx = (A.fU[c] - C.fU[c]) + (B.fD[c] - Dd.fD[c]);
         const double gy = (A.gR[c] - B.gR[c]) + (C.gL[c] - Dd.gL[c]);
-        const double abar = std::fma(hy, gy, std::fma(hx, fx, h));
-        ab[c] = abar;
+        ab[c] = std::fma(hy, gy, std::fma(hx, fx, h));
         // Eq. 2DDerivatives, total order n = P down to 1
-        double D[PMAX + 1][PMAX + 1] = {};
         for (int n = P; n >= 1; --n)
           for (int l = 0; l <= n; ++l) {
             const int k = n - l;
@@ -442,33 +519,47 @@ void half_step(const wcc2d_oracle_problem& pb, int parity, const double* qin, do
             if (k >= 1) {
               const int kb = k - 1, r = P - kb - l;
               X = 0.5 * ((C.V[c][kb][l] - A.V[c][kb][l]) + (Dd.V[c][kb][l] - B.V[c][kb][l]));
-              for (int s = 3; s <= r; s += 2) X = std::fma(K.CX1[s], D[kb + s][l], X);
+              for (int s = 3; s <= r; s += 2) X = std::fma(K.CX1[s], D[c][kb + s][l], X);
               for (int t = 2; t <= r; t += 2)
-                for (int s = 1; s <= r - t; s += 2) X = std::fma(K.CX2[s][t], D[kb + s][l + t], X);
+                for (int s = 1; s <= r - t; s += 2) X = std::fma(K.CX2[s][t], D[c][kb + s][l + t], X);
             }
             if (l >= 1) {
               const int lb = l - 1, r = P - k - lb;
               Y = 0.5 * ((B.V[c][k][lb] - A.V[c][k][lb]) + (Dd.V[c][k][lb] - C.V[c][k][lb]));
-              for (int t = 3; t <= r; t += 2) Y = std::fma(K.CX1[t], D[k][lb + t], Y);
+              for (int t = 3; t <= r; t += 2) Y = std::fma(K.CX1[t], D[c][k][lb + t], Y);
               for (int t = 1; t <= r; t += 2)
-                for (int s = 2; s <= r - t; s += 2) Y = std::fma(K.CX2[t][s], D[k + s][lb + t], Y);
+                for (int s = 2; s <= r - t; s += 2) Y = std::fma(K.CX2[t][s], D[c][k + s][lb + t], Y);
             }
-            D[k][l] = (k >= 1 && l >= 1) ? 0.5 * (X + Y) : (k >= 1 ? X : Y);
+            D[c][k][l] = (k >= 1 && l >= 1) ? 0.5 * (X + Y) : (k >= 1 ? X : Y);
           }
-        if (pb.limiter && P >= 1 && pb.equation != EQ_EULER)
-          limit2d(P, pb.eps, abar, D, A.V[c][0][0], C.V[c][0][0], Dd.V[c][0][0], B.V[c][0][0]);
-        double pv = abar;
+      }
+      if (pb.limiter && P >= 1) {
+        if (pb.equation == EQ_EULER) {
+          double vtx[4][4];
+          for (int c = 0; c < 4; ++c) {
+            vtx[c][0] = A.V[c][0][0];
+            vtx[c][1] = C.V[c][0][0];
+            vtx[c][2] = Dd.V[c][0][0];
+            vtx[c][3] = B.V[c][0][0];
+          }
+          char_limit2d(P, pb.gamma, pb.eps, dx, dy, ab, D, vtx);
+        } else {
+          limit2d(P, pb.eps, ab[0], D[0], A.V[0][0][0], C.V[0][0][0], Dd.V[0][0][0], B.V[0][0][0]);
+        }
+      }
+      for (int c = 0; c < nc; ++c) {
+        double pv = ab[c];
         for (int n = 2; n <= P; ++n)
           for (int l = 0; l <= n; ++l) {
             const int k = n - l;
-            if (k % 2 == 0 && l % 2 == 0) pv = std::fma(K.NQA[k][l], D[k][l], pv);
+            if (k % 2 == 0 && l % 2 == 0) pv = std::fma(K.NQA[k][l], D[c][k][l], pv);
           }
         const int64_t cell = j * pb.Nx + i;
         qout[((int64_t)(c * nd)) * plane + cell] = pv;
         bool ok = std::isfinite(pv);
         for (int n = 1; n <= P; ++n)
           for (int l = 0; l <= n; ++l) {
-            const double x = D[n - l][l];
+            const double x = D[c][n - l][l];
             qout[((int64_t)(c * nd + dof(n - l, l))) * plane + cell] = x;
             ok = ok && std::isfinite(x);
           }
@@ -548,7 +639,6 @@ int32_t wcc2d_oracle_old_cell(const wcc2d_oracle_problem* pb, const double* q, d
 int32_t wcc2d_oracle_half_step(const wcc2d_oracle_problem* pb, int32_t parity, const double* qin, double dt,
                                double* qout, double* smax, int32_t* flags) {
   if (!pb || pb->P < 0 || pb->P > w2d::PMAX || pb->Nx < 2 || pb->Ny < 2) return -1;
-  if (pb->equation == w2d::EQ_EULER && pb->limiter) return -1;
   int fl = 0;
   w2d::half_step(*pb, parity, qin, dt, qout, smax, &fl);
   if (flags) *flags = fl;
@@ -562,7 +652,6 @@ int32_t wcc2d_oracle_half_step(const wcc2d_oracle_problem* pb, int32_t parity, c
 int64_t wcc2d_oracle_run(const wcc2d_oracle_problem* pb, int32_t* parity, double* t, double* smax, double* q,
                          double t_end, double cfl, double dt_fixed, int64_t max_half_steps, int32_t* flags) {
   if (!pb || pb->P < 0 || pb->P > w2d::PMAX || pb->Nx < 2 || pb->Ny < 2) return -1;
-  if (pb->equation == w2d::EQ_EULER && pb->limiter) return -1;
   const size_t n = (size_t)(w2d::ncomp(*pb) * w2d::ndof(pb->P)) * (size_t)(pb->Nx * pb->Ny);
   std::vector<double> tmp(n);
   int64_t taken = 0;

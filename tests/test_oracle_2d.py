@@ -1,8 +1,10 @@
 """Pins of the 2D oracle (Section 3, Appendix B; the unlimited 2D Euler step
 of Section 4), each fixed by something other than the oracle's own formulas:
 
-* Table 3 (Section 5.3.1): density errors of LCCS-2/3/4 on the isentropic
-  vortex at t = 2, mesh sizes 1/5 and 1/10 (printed to 3 digits).
+* Table 3 (Section 5.3.1): density errors of LCCS-2/3/4 and of WCCS-2/3/4
+  (limiter on the characteristic fields of the rotated decomposition of
+  Section 4) on the isentropic vortex at t = 2, mesh sizes 1/5 and 1/10
+  (printed to 3 digits).
 * Exactness for polynomial data of degree <= P under linear advection, on
   every cell outside the periodic seam's domain of dependence.
 * P = 0 is the 2D staggered Lax-Friedrichs scheme.
@@ -44,9 +46,15 @@ TABLE3_LCCS = {  # (P, N): (L1, Linf) of density, mesh size 10/N
 }
 
 
-def vortex_errors(P, N):
+TABLE3_WCCS = {  # limited, rotated characteristic decomposition (Section 4)
+    (1, 50): (1.69e-3, 3.77e-2), (2, 50): (4.09e-4, 6.91e-3), (3, 50): (5.70e-5, 7.25e-4),
+    (1, 100): (2.75e-4, 9.63e-3), (2, 100): (5.26e-5, 9.30e-4), (3, 100): (2.16e-6, 3.41e-5),
+}
+
+
+def vortex_errors(P, N, limiter=False):
     q0 = inputs.isentropic_vortex(P, N)
-    pb = oracle.Problem2D("euler", P, N, N, limiter=False, x_left=-5, x_right=5, y_left=-5, y_right=5)
+    pb = oracle.Problem2D("euler", P, N, N, limiter=limiter, x_left=-5, x_right=5, y_left=-5, y_right=5)
     r = oracle.run2d(pb, q0, t_end=2.0, cfl=CFL[P])
     assert r.flags == 0 and r.t == 2.0
     X, Y = inputs.centers2d(-5, 5, -5, 5, N, N, r.parity)
@@ -67,6 +75,23 @@ def test_table3_lccs_mesh_1_5(P):
 def test_table3_lccs_mesh_1_10(P):
     l1, linf = vortex_errors(P, 100)
     p1, pinf = TABLE3_LCCS[(P, 100)]
+    assert abs(l1 / p1 - 1) < 0.04, (l1, p1)
+    assert abs(linf / pinf - 1) < 0.04, (linf, pinf)
+
+
+@pytest.mark.parametrize("P", [1, 2, 3])
+def test_table3_wccs_mesh_1_5(P):
+    l1, linf = vortex_errors(P, 50, limiter=True)
+    p1, pinf = TABLE3_WCCS[(P, 50)]
+    assert abs(l1 / p1 - 1) < 0.04, (l1, p1)
+    assert abs(linf / pinf - 1) < 0.04, (linf, pinf)
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("P", [1, 2])
+def test_table3_wccs_mesh_1_10(P):
+    l1, linf = vortex_errors(P, 100, limiter=True)
+    p1, pinf = TABLE3_WCCS[(P, 100)]
     assert abs(l1 / p1 - 1) < 0.04, (l1, p1)
     assert abs(linf / pinf - 1) < 0.04, (linf, pinf)
 

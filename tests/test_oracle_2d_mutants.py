@@ -16,10 +16,10 @@ MUTANTS = {
     "flux integral 2^s dropped": ("FI[k][l] = 1.0 / ((double)(k + 1) * std::ldexp(1.0, k) * (double)(l + 1));",
                                   "FI[k][l] = 1.0 / ((double)(k + 1) * (double)(l + 1));"),
     "CK y factor index": ("std::fma(cy[l][m], G[c][k][l + 1][m - 1]", "std::fma(cy[k][m], G[c][k][l + 1][m - 1]"),
-    "cross derivative not averaged": ("D[k][l] = (k >= 1 && l >= 1) ? 0.5 * (X + Y)",
-                                      "D[k][l] = (k >= 1 && l >= 1) ? X"),
-    "y correction index": ("Y = std::fma(K.CX2[t][s], D[k + s][lb + t], Y);",
-                           "Y = std::fma(K.CX2[t][s], D[k + t][lb + s], Y);"),
+    "cross derivative not averaged": ("D[c][k][l] = (k >= 1 && l >= 1) ? 0.5 * (X + Y)",
+                                      "D[c][k][l] = (k >= 1 && l >= 1) ? X"),
+    "y correction index": ("Y = std::fma(K.CX2[t][s], D[c][k + s][lb + t], Y);",
+                           "Y = std::fma(K.CX2[t][s], D[c][k + t][lb + s], Y);"),
     "vertex value factorial": ("o.V[c][k][l] = (k <= 1 && l <= 1) ? s : K.FF[k][l] * s;", "o.V[c][k][l] = s;"),
     "candidate slope vertex": ("a2 - (vld + vrd), vru - vrd", "a2 - (vld + vru), vru - vrd"),
     "sigma vertex sign": ("const int sx[4] = {-1, 1, 1, -1}", "const int sx[4] = {1, 1, 1, -1}"),
@@ -33,12 +33,20 @@ MUTANTS = {
     "point value sign": ("NQA[k][l] = (k % 2 == 0 && l % 2 == 0) ? -QA[k][l] : 0.0;",
                          "NQA[k][l] = (k % 2 == 0 && l % 2 == 0) ? QA[k][l] : 0.0;"),
     "limited x slope candidate": ("dx1 = std::fma(w[m], ux[m], dx1);", "dx1 = std::fma(w[m], uy[m], dx1);"),
+    "rotated direction from rho": ("const double gx = D[3][1][0] / dx, gy = D[3][0][1] / dy;",
+                                   "const double gx = D[0][1][0] / dx, gy = D[0][0][1] / dy;"),
+    "rotated direction swapped": ("nx = gx / gn;\n    ny = gy / gn;", "nx = gy / gn;\n    ny = gx / gn;"),
+    "left eigenvector sign": ("{-ut, -ny, nx, 0.0}", "{ut, -ny, nx, 0.0}"),
+    "right eigenvector energy entry": ("{1.0, u, vv, 0.5 * q2}", "{1.0, u, vv, q2}"),
+    "tangential velocity sign": ("ut = std::fma(vv, nx, -(u * ny))", "ut = std::fma(vv, nx, u * ny)"),
 }
 
 
 def quick_pins() -> list:
     checks = [
         ("table3 P2", lambda: t2.test_table3_lccs_mesh_1_5(2)),
+        ("table3 WCCS P1", lambda: t2.test_table3_wccs_mesh_1_5(1)),
+        ("table3 WCCS P2", lambda: t2.test_table3_wccs_mesh_1_5(2)),
         ("exactness P3", lambda: t2.test_polynomial_exactness_advection(3)),
         ("LxF", lambda: [t2.test_p0_is_staggered_lax_friedrichs(e, p) for e in ("advection", "burgers") for p in (0, 1)]),
         ("1D x", lambda: t2.test_reduces_to_1d_scalar("burgers", 3, "x")),
