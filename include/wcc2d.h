@@ -1,6 +1,6 @@
 /* wcc2d.h -- C ABI of the 2D half-step of the weighted compact central (WCC)
  * schemes (Shen & Parsani, arXiv:2104.04347, Section 3 and Appendix B; the
- * unlimited 2D Euler step of Section 4) on gfx950.
+ * 2D Euler step of Section 4) on gfx950.
  *
  * The library advances u_t + f(u)_x + g(u)_y = 0 (Eq. 2DHCL) on a periodic
  * rectangle [x_left, x_right] x [y_left, y_right] with Nx x Ny cells, on the
@@ -10,16 +10,17 @@
  * space-time flux averages (Eq. SubEq:2DFluxFU/FD/GR/GL) combined into the new
  * cell average (Eq. 2DIntegral), the new derivatives from the vertex values at
  * the half time level (Eq. 2DDerivatives with Eq. SubEq:2DUij; cross
- * derivatives averaged) and, for scalar equations, the 2D limiter of
- * Section 3.2.
+ * derivatives averaged) and the 2D limiter of Section 3.2 -- for the Euler
+ * equations applied to characteristic fields in the rotated direction of
+ * the gradient of rho e (Section 4, Eq. RotatedNormal).
  *
  * Conventions
  * -----------
  * - Return codes, ownership and stream order are those of wcc.h (same
  *   WCC_* codes; wcc_strerror names them).
  * - Equations: WCC_ADVECTION (f = a u, g = b u), WCC_BURGERS
- *   (f = g = u^2/2), WCC_EULER (rho, rho u, rho v, rho e; gamma-law gas;
- *   limiter not available: the LCCS form).
+ *   (f = g = u^2/2), WCC_EULER (rho, rho u, rho v, rho e; gamma-law gas);
+ *   limiter 0 gives the unlimited LCCS form, 1 the WCCS form.
  * - State layout at the boundary: host doubles indexed
  *   [c][d][j][i] = host[((c*ndof + d)*Ny + j)*Nx + i], ndof = (P+1)(P+2)/2,
  *   with the DOFs u_{kx,ly} = dx^k dy^l d^{k+l}u/dx^k dy^l at the cell
@@ -55,7 +56,7 @@ typedef struct {
   double a, b;                                /* advection velocity, default (1, 1) */
   double gamma;                               /* Euler, default 1.4 */
   double eps;                                 /* limiter epsilon, default 1e-40 (Section 3.2) */
-  int32_t limiter;                            /* 0/1, default 1; scalar equations only */
+  int32_t limiter;                            /* 0/1, default 1 */
   int32_t reserved;
 } wcc2d_params;
 
@@ -74,8 +75,8 @@ int wcc2d_params_default(wcc2d_params* p);
 
 /* New context for equation (WCC_ADVECTION, WCC_BURGERS, WCC_EULER), degree
  * P in [0, WCC2D_PMAX], Nx, Ny >= 2 cells with Nx*Ny <= 2^28.  params may be
- * null (defaults).  Errors: WCC_EINVAL for bad sizes, enums or domain, a
- * limiter requested for Euler, gamma <= 1 for Euler. */
+ * null (defaults).  Errors: WCC_EINVAL for bad sizes, enums or domain,
+ * gamma <= 1 for Euler. */
 int wcc2d_create(int equation, int P, int64_t Nx, int64_t Ny, const wcc2d_params* params, wcc2d_ctx** out);
 
 /* Device bytes the caller must provide to wcc2d_bind: a control block, the

@@ -1,7 +1,8 @@
 // wcc2d_oracle.cpp -- plain FP64 CPU reference of the 2D weighted compact
 // central (WCC) half-step on Cartesian meshes (Section 3 and Appendix B of
-// Shen & Parsani, arXiv:2104.04347), and of the unlimited 2D Euler half-step
-// (the LCCS form of Section 4 on the 2D system).
+// Shen & Parsani, arXiv:2104.04347), including the 2D Euler half-step of
+// Section 4, unlimited (LCCS) or limited in the rotated characteristic
+// decomposition (WCCS).
 //
 // TEST INFRASTRUCTURE ONLY, like the 1D oracle in this directory: tests, the
 // smoke check and the CPU-baseline leg of the benchmark use it; the product

@@ -234,7 +234,7 @@ int wcc2d_create(int equation, int P, int64_t Nx, int64_t Ny, const wcc2d_params
   wcc2d_params prm;
   if (params) prm = *params; else wcc2d_params_default(&prm);
   if (!(prm.x_right > prm.x_left) || !(prm.y_right > prm.y_left) || !(prm.eps >= 0.0)) return WCC_EINVAL;
-  if (equation == WCC_EULER && (prm.limiter || !(prm.gamma > 1.0))) return WCC_EINVAL;
+  if (equation == WCC_EULER && !(prm.gamma > 1.0)) return WCC_EINVAL;
   wcc2d_ctx* c = new wcc2d_ctx();
   c->eq = equation;
   c->P = P;

@@ -1,5 +1,5 @@
 // wcc2d_cell.hpp -- per-cell arithmetic of the 2D WCC half-step (Section 3,
-// Appendix B; the unlimited 2D Euler step of Section 4), binary64.
+// Appendix B; the 2D Euler step of Section 4), binary64.
 //
 // State of a cell: the point value and the scaled derivatives
 // u_{kx,ly} = dx^k dy^l d^{k+l}u/dx^k dy^l at the centre, k + l <= P, stored
@@ -335,6 +335,83 @@ __device__ __forceinline__ void limit2d(double eps, double abar, double (&D)[P +
   for (int n = 2; n <= P; ++n)
 #pragma unroll
     for (int l = 0; l <= n; ++l) D[n - l][l] = w0 * D[n - l][l];
+}
+
+// Rotated characteristic limiting of a 2D Euler new cell (Section 4): the
+// direction n = grad(phi)/|grad(phi)| with phi = rho e from the new cell's
+// central-difference derivatives (Eq. RotatedNormal; n = (1, 0) where the
+// gradient vanishes); the eigenvectors of A cos(theta) + B sin(theta) at the
+// new average; every characteristic field through limit2d; back with R.
+// v[c][vtx]: vertex values, vtx = LD, RD, RU, LU.
+template <int P>
+__device__ __forceinline__ void char_limit2d(const Phys2& ph, double dx, double dy, const double (&ab)[4],
+                                             double (&D)[4][P + 1][P + 1], const double (&v)[4][4]) {
+  const double gx = D[3][1][0] / dx, gy = D[3][0][1] / dy;
+  const double g2 = __builtin_fma(gy, gy, gx * gx);
+  double nx = 1.0, ny = 0.0;
+  if (g2 > 0.0) {
+    const double gn = __builtin_sqrt(g2);
+    nx = gx / gn;
+    ny = gy / gn;
+  }
+  const double rho = ab[0], u = ab[1] / rho, vv = ab[2] / rho;
+  const double p = ph.gm1 * (ab[3] - 0.5 * __builtin_fma(ab[2], vv, ab[1] * u));
+  const double c = __builtin_sqrt((ph.gamma * p) / rho);
+  const double H = (ab[3] + p) / rho;
+  const double un = __builtin_fma(vv, ny, u * nx), ut = __builtin_fma(vv, nx, -(u * ny));
+  const double q2 = __builtin_fma(vv, vv, u * u);
+  const double ic = 1.0 / c;
+  const double b1 = ph.gm1 * (ic * ic), b2 = 0.5 * (q2 * b1);
+  const double uic = un * ic, nxic = nx * ic, nyic = ny * ic, b1u = b1 * u, b1v = b1 * vv;
+  const double L[4][4] = {{0.5 * (b2 + uic), -0.5 * (b1u + nxic), -0.5 * (b1v + nyic), 0.5 * b1},
+                          {1.0 - b2, b1u, b1v, -b1},
+                          {-ut, -ny, nx, 0.0},
+                          {0.5 * (b2 - uic), -0.5 * (b1u - nxic), -0.5 * (b1v - nyic), 0.5 * b1}};
+  const double cun = c * un;
+  const double R[4][4] = {{1.0, u - c * nx, vv - c * ny, H - cun},
+                          {1.0, u, vv, 0.5 * q2},
+                          {0.0, -ny, nx, ut},
+                          {1.0, u + c * nx, vv + c * ny, H + cun}};
+  double out[4][P + 1][P + 1];
+#pragma unroll
+  for (int f = 0; f < 4; ++f) {
+    auto proj = [&](double x0, double x1, double x2, double x3) {
+      double s = L[f][0] * x0;
+      s = __builtin_fma(L[f][1], x1, s);
+      s = __builtin_fma(L[f][2], x2, s);
+      if (f != 2) s = __builtin_fma(L[f][3], x3, s);
+      return s;
+    };
+    const double ca = proj(ab[0], ab[1], ab[2], ab[3]);
+    double cv[4];
+#pragma unroll
+    for (int vtx = 0; vtx < 4; ++vtx) cv[vtx] = proj(v[0][vtx], v[1][vtx], v[2][vtx], v[3][vtx]);
+    double cD[P + 1][P + 1];
+#pragma unroll
+    for (int n = 1; n <= P; ++n)
+#pragma unroll
+      for (int l = 0; l <= n; ++l) cD[n - l][l] = proj(D[0][n - l][l], D[1][n - l][l], D[2][n - l][l], D[3][n - l][l]);
+    limit2d<P>(ph.eps, ca, cD, cv[0], cv[1], cv[2], cv[3]);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      if (f == 2 && r == 0) continue;
+#pragma unroll
+      for (int n = 1; n <= P; ++n)
+#pragma unroll
+        for (int l = 0; l <= n; ++l) {
+          const int k = n - l;
+          out[r][k][l] = (f == 0) ? R[f][r] * cD[k][l] : __builtin_fma(R[f][r], cD[k][l], out[r][k][l]);
+        }
+    }
+    // keep the four fields in sequence (register pressure)
+    __builtin_amdgcn_sched_barrier(0);
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+#pragma unroll
+    for (int n = 1; n <= P; ++n)
+#pragma unroll
+      for (int l = 0; l <= n; ++l) D[r][n - l][l] = out[r][n - l][l];
 }
 
 // New derivatives of one component, highest total order first (Eq.

@@ -1,5 +1,5 @@
 // wcc2d_kernels.hip -- the fused 2D half-step kernel for gfx950 (Section 3,
-// Appendix B; the unlimited 2D Euler step).
+// Appendix B; the 2D Euler step of Section 4).
 //
 // Work decomposition:
 //   * a wavefront owns an 8 x 8 tile of OLD cells (lane = 8*ly + lx) and
@@ -54,6 +54,54 @@ __device__ __forceinline__ void run_tile2(const Step2Args& a, int tile, int tile
   const bool mine = lx < 7 && ly < 7 && ni < a.Nx && nj < a.Ny;
   const uint32_t ncell = (uint32_t)(nj * a.Nx + ni);
   double ab[NC];
+  if constexpr (EQ == kEuler && LIM && P >= 1) {
+    // the characteristic limiter couples the components: form all four new
+    // averages and derivatives first
+    double D[4][P + 1][P + 1], vx[4][4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const double B_RD = __shfl(o.RD[c], lane + 8, 64), B_fD = __shfl(o.fD[c], lane + 8, 64),
+                   B_gR = __shfl(o.gR[c], lane + 8, 64);
+      const double C_LU = __shfl(o.LU[c], lane + 1, 64), C_fU = __shfl(o.fU[c], lane + 1, 64),
+                   C_gL = __shfl(o.gL[c], lane + 1, 64);
+      const double E_LD = __shfl(o.LD[c], lane + 9, 64), E_fD = __shfl(o.fD[c], lane + 9, 64),
+                   E_gL = __shfl(o.gL[c], lane + 9, 64);
+      double VB[NV], VC[NV], VE[NV];
+#pragma unroll
+      for (int d = 0; d < NV; ++d) {
+        VB[d] = __shfl(o.V[c][d], lane + 8, 64);
+        VC[d] = __shfl(o.V[c][d], lane + 1, 64);
+        VE[d] = __shfl(o.V[c][d], lane + 9, 64);
+      }
+      const double h = 0.25 * (((o.RU[c] + B_RD) + C_LU) + E_LD);
+      const double fx = (o.fU[c] - C_fU) + (B_fD - E_fD);
+      const double gy = (o.gR[c] - B_gR) + (C_gL - E_gL);
+      ab[c] = __builtin_fma(hy, gy, __builtin_fma(hx, fx, h));
+      new_derivatives<P>(o.V[c], VB, VC, VE, D[c]);
+      vx[c][0] = o.V[c][0];
+      vx[c][1] = VC[0];
+      vx[c][2] = VE[0];
+      vx[c][3] = VB[0];
+    }
+    char_limit2d<P>(a.ph, a.dx, a.dy, ab, D, vx);
+    if (mine) {
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const double pv = point_value<P>(ab[c], D[c]);
+        bool ok = __builtin_isfinite(pv);
+        wcc::row_store(wcc::row_base(a.q_new + (int64_t)(c * ND) * a.plane), ncell, pv);
+#pragma unroll
+        for (int n = 1; n <= P; ++n)
+#pragma unroll
+          for (int l = 0; l <= n; ++l) {
+            const double x = D[c][n - l][l];
+            ok = ok && __builtin_isfinite(x);
+            wcc::row_store(wcc::row_base(a.q_new + (int64_t)(c * ND + dof(n - l, l)) * a.plane), ncell, x);
+          }
+        if (!ok) flags |= 1u;
+      }
+    }
+  } else {
 #pragma unroll
   for (int c = 0; c < NC; ++c) {
     // right / upper parents' halves of this component
@@ -78,7 +126,7 @@ __device__ __forceinline__ void run_tile2(const Step2Args& a, int tile, int tile
     ab[c] = abar;
     double D[P + 1][P + 1];
     if constexpr (P >= 1) new_derivatives<P>(o.V[c], VB, VC, VE, D);
-    if constexpr (LIM && P >= 1 && EQ != kEuler) limit2d<P>(a.ph.eps, abar, D, o.V[c][0], VC[0], VE[0], VB[0]);
+    if constexpr (LIM && P >= 1) limit2d<P>(a.ph.eps, abar, D, o.V[c][0], VC[0], VE[0], VB[0]);
     const double pv = point_value<P>(abar, D);
     if (mine) {
       bool ok = __builtin_isfinite(pv);
@@ -93,6 +141,7 @@ __device__ __forceinline__ void run_tile2(const Step2Args& a, int tile, int tile
         }
       if (!ok) flags |= 1u;
     }
+  }
   }
   if (mine) {
     const double sr = speed_rate<EQ>(ab, a.ph, a.idx, a.idy, flags);
@@ -156,7 +205,7 @@ __global__ __launch_bounds__(256) void k2d_state_speed(const Step2Args a) {
 
 template <int EQ, int P>
 static hipError_t launch_ep(const Step2Args& a, bool lim, int blocks, int threads, hipStream_t s) {
-  if (lim && EQ != kEuler)
+  if (lim)
     hipLaunchKernelGGL((k2d_half_step<EQ, P, true>), dim3(blocks), dim3(threads), 0, s, a);
   else
     hipLaunchKernelGGL((k2d_half_step<EQ, P, false>), dim3(blocks), dim3(threads), 0, s, a);
@@ -178,7 +227,7 @@ hipError_t launch_half_step2(const Step2Args& a, int eq, int P, bool lim, int bl
   switch (eq) {
     case kAdvection: return launch_e<kAdvection>(a, P, lim, blocks, threads, s);
     case kBurgers: return launch_e<kBurgers>(a, P, lim, blocks, threads, s);
-    case kEuler: return launch_e<kEuler>(a, P, false, blocks, threads, s);
+    case kEuler: return launch_e<kEuler>(a, P, lim, blocks, threads, s);
   }
   return hipErrorInvalidValue;
 }
@@ -206,7 +255,7 @@ hipError_t launch_state_speed2(const Step2Args& a, int eq, int P, int blocks, hi
 
 template <int EQ, int P>
 static hipError_t occ_ep(bool lim, int threads, int* per_cu) {
-  if (lim && EQ != kEuler)
+  if (lim)
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k2d_half_step<EQ, P, true>, threads, 0);
   return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k2d_half_step<EQ, P, false>, threads, 0);
 }
@@ -226,7 +275,7 @@ hipError_t occupancy_half_step2(int eq, int P, bool lim, int threads, int* per_c
   switch (eq) {
     case kAdvection: return occ_e<kAdvection>(P, lim, threads, per_cu);
     case kBurgers: return occ_e<kBurgers>(P, lim, threads, per_cu);
-    case kEuler: return occ_e<kEuler>(P, false, threads, per_cu);
+    case kEuler: return occ_e<kEuler>(P, lim, threads, per_cu);
   }
   return hipErrorInvalidValue;
 }

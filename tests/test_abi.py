@@ -104,8 +104,12 @@ def test_2d_create_validates():
     assert p.limiter == 1 and p.eps == 1e-40 and p.x_right == 1.0 and p.b == 1.0
     for eq, P, nx, ny in [(3, 2, 64, 64), (0, 4, 64, 64), (0, -1, 64, 64), (0, 2, 1, 64), (0, 2, 1 << 15, 1 << 14)]:
         assert lib.wcc2d_create(eq, P, nx, ny, ctypes.byref(p), ctypes.byref(h)) == binding.WCC_EINVAL
-    # Euler: the limiter is not available in 2D (unlimited form only)
+    # Euler needs gamma > 1; with it, both the limited and the unlimited form exist
+    p.gamma = 1.0
     assert lib.wcc2d_create(2, 2, 64, 64, ctypes.byref(p), ctypes.byref(h)) == binding.WCC_EINVAL
+    p.gamma = 1.4
+    assert lib.wcc2d_create(2, 2, 64, 64, ctypes.byref(p), ctypes.byref(h)) == 0
+    lib.wcc2d_destroy(h)
     p.limiter = 0
     assert lib.wcc2d_create(2, 3, 100, 50, ctypes.byref(p), ctypes.byref(h)) == 0
     nb = ctypes.c_size_t()

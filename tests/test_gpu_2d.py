@@ -1,7 +1,8 @@
-"""GPU parity of the 2D half-step (Section 3, Appendix B; unlimited 2D Euler)
+"""GPU parity of the 2D half-step (Section 3, Appendix B; 2D Euler, Section 4)
 against the 2D oracle: bit for bit (binary64, the same written operation
 order on both sides), on ragged tile edges, meshes narrower than a tile,
-graph-replayed runs and the Euler vortex of Table 3."""
+graph-replayed runs and the Euler vortex of Table 3, unlimited and with the
+rotated characteristic limiter."""
 import numpy as np
 import pytest
 
@@ -103,6 +104,34 @@ def test_euler_vortex_bitwise(P):
     q, info = gpu_run("euler", P, N, N, q0, False, dom=dom, cfl=CFL[P], t_end=2.0)
     r = oracle_run("euler", P, N, N, q0, False, dom=dom, cfl=CFL[P], t_end=2.0)
     assert_bitwise(q, info, r, f"vortex P={P}")
+
+
+@pytest.mark.parametrize("P", [1, 2, 3])
+def test_euler_vortex_limited_bitwise(P):
+    """Table 3's WCCS setup: the same vortex with the rotated characteristic
+    limiter of Section 4."""
+    N = 50
+    q0 = inputs.isentropic_vortex(P, N)
+    dom = (-5.0, 5.0, -5.0, 5.0)
+    q, info = gpu_run("euler", P, N, N, q0, True, dom=dom, cfl=CFL[P], t_end=2.0)
+    r = oracle_run("euler", P, N, N, q0, True, dom=dom, cfl=CFL[P], t_end=2.0)
+    assert_bitwise(q, info, r, f"limited vortex P={P}")
+
+
+@pytest.mark.parametrize("P", [1, 3])
+def test_euler_modes_limited_bitwise(P):
+    """A positive Euler state with gradients of rho e in every direction on a
+    ragged mesh, limited, with a uniform patch inside (zero gradient of
+    rho e: the rotated direction falls back to (1, 0)) whose edges are
+    jumps."""
+    Nx, Ny = 23, 30
+    q0 = np.concatenate([inputs.taylor2d(inputs.modes2d(seed, c0=c0, amp=amp), P, Nx, Ny)
+                         for seed, c0, amp in ((11, 2.0, 0.5), (12, 0.0, 0.3), (13, 0.0, 0.3), (14, 6.0, 1.0))])
+    q0[:, 0, 5:9, 4:10] = q0[:, 0, 5:6, 4:5]
+    q0[:, 1:, 5:9, 4:10] = 0.0
+    q, info = gpu_run("euler", P, Nx, Ny, q0, True, cfl=CFL[P], half_steps=20)
+    r = oracle_run("euler", P, Nx, Ny, q0, True, cfl=CFL[P], half_steps=20)
+    assert_bitwise(q, info, r, f"limited modes P={P}")
 
 
 def test_2d_errors():

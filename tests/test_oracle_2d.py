@@ -1,5 +1,5 @@
-"""Pins of the 2D oracle (Section 3, Appendix B; the unlimited 2D Euler step
-of Section 4), each fixed by something other than the oracle's own formulas:
+"""Pins of the 2D oracle (Section 3, Appendix B; the 2D Euler step of
+Section 4, unlimited and limited), each fixed by something other than the oracle's own formulas:
 
 * Table 3 (Section 5.3.1): density errors of LCCS-2/3/4 and of WCCS-2/3/4
   (limiter on the characteristic fields of the rotated decomposition of
