@@ -170,8 +170,9 @@ def time_batch(args):
 def time_2d(args):
     """The 2D half-step (Section 3): Burgers with the limiter, P = 3, on a
     2048 x 2048 periodic mesh of [0, 2]^2 with seeded sine modes; and the
-    unlimited Euler isentropic vortex of Table 3, P = 3, 1024 x 1024 on
-    [-5, 5]^2.  Binary64.  Algorithmic bytes per launch: every old cell read
+    Euler isentropic vortex of Table 3, P = 3, 1024 x 1024 on [-5, 5]^2,
+    unlimited (LCCS) and with the rotated characteristic limiter (WCCS).
+    Binary64.  Algorithmic bytes per launch: every old cell read
     once and every new cell written once, nc * ndof doubles each."""
     import torch
     from paper_2104_04347_amd import binding, inputs
@@ -179,6 +180,8 @@ def time_2d(args):
     cases = [("burgers_lim_P3", "burgers", 3, args.n2d, True, (0.0, 2.0, 0.0, 2.0), 0.25,
               lambda: inputs.taylor2d(inputs.modes2d(args.seed), 3, args.n2d, args.n2d)),
              ("euler_vortex_P3", "euler", 3, args.n2d_euler, False, (-5.0, 5.0, -5.0, 5.0), 0.25,
+              lambda: inputs.isentropic_vortex(3, args.n2d_euler)),
+             ("euler_vortex_lim_P3", "euler", 3, args.n2d_euler, True, (-5.0, 5.0, -5.0, 5.0), 0.25,
               lambda: inputs.isentropic_vortex(3, args.n2d_euler))]
     for name, eq, P, N, lim, dom, cfl, make in cases:
         q0 = make()
