@@ -11,7 +11,7 @@ Section 5 (0.4 / 0.3 / 0.25 per half-step for WCCS-2 / 3 / 4), limiter on:
 * Titarev-Toro modified Shu-Osher problem (Section 5.2): [-5, 5]
   transmissive, dx = 1/200, t = 5; density errors against our own fine-grid
   run (oracle, WCCS-4, dx = 1/1000; the paper's reference is a WENO-Z run on
-  the same dx, a comparison system outside this build).
+  the same dx, a comparison system this library does not include).
 
 Recorded per run: the number of half-steps, the final parity and time, the
 SHA-256 of the final state (float64, C order, shape (nc, P+1, n)) so that a

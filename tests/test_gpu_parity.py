@@ -155,7 +155,7 @@ def test_c1_advection_full():
     kw = dict(x_left=0.0, x_right=2.0, a=1.0)
     q, info, taken = gpu_run("advection", P, N, "periodic", q0, limiter=False, t_end=2.0, cfl=0.25, **kw)
     ref = oracle_run("advection", P, N, "periodic", q0, limiter=False, t_end=2.0, cfl=0.25, **kw)
-    assert_bitwise(q, info, taken, ref, "C1")
+    assert_bitwise(q, info, taken, ref, "advection N=200 t=2")
     x = inputs.centers(0.0, 2.0, N, N, info.parity)
     assert np.abs(q[0, 0] - fn(x - 2.0)).mean() < 2e-6
 
@@ -168,7 +168,7 @@ def test_c2_burgers_full_size():
     kw = dict(x_left=0.0, x_right=2.0)
     q, info, taken = gpu_run("burgers", P, N, "periodic", q0, limiter=True, steps=1500, cfl=0.25, **kw)
     ref = oracle_run("burgers", P, N, "periodic", q0, limiter=True, steps=1500, cfl=0.25, **kw)
-    assert_bitwise(q, info, taken, ref, "C2")
+    assert_bitwise(q, info, taken, ref, "Burgers N=12800")
 
 
 @pytest.mark.parametrize("P", [2, 3])
@@ -180,7 +180,7 @@ def test_c3_euler_full_size(P):
     q0, _ = inputs.euler_riemann(0, P, N)
     q, info, taken = gpu_run("euler", P, N, "transmissive", q0, limiter=True, steps=6, cfl=0.25)
     ref = oracle_run("euler", P, N, "transmissive", q0, limiter=True, steps=6, cfl=0.25)
-    assert_bitwise(q, info, taken, ref, f"C3 P={P}")
+    assert_bitwise(q, info, taken, ref, f"Euler N=2^20 P={P}")
 
 
 def test_graph_replay_equals_single_steps():

@@ -80,8 +80,9 @@ def test_euler_gamma3_simple_wave_order(P):
 
 @pytest.mark.parametrize("P,lim", [(1, False), (2, False), (3, False), (4, False)])
 def test_burgers_before_shock_order(P, lim):
-    """C2-type data (seeded sum of three sines around 0.5 on [0, 2]) up to half
-    the breaking time, against the method of characteristics.  Limiter off: the
+    """Burgers data of the benchmark kind (seeded sum of three sines around
+    0.5 on [0, 2]) up to half the breaking time, against the method of
+    characteristics.  Limiter off: the
     paper's order argument for the limiter (Eq. 1DWmError) assumes beta_m of
     the linear candidates scales like dx^2; where a candidate's slope passes
     through zero the weights are not small and the limiter does act on this
