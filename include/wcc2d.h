@@ -109,9 +109,14 @@ int wcc2d_advance(wcc2d_ctx* c, double t_end, double cfl, int64_t max_half_steps
  * and fill info (if non-null); synchronises the stream. */
 int wcc2d_read_dofs(wcc2d_ctx* c, double* host, int64_t cap, wcc2d_state_info* info);
 
-/* Launch shape: threads per block (64..256, multiple of 64; 0 = 256) and
- * blocks per launch (0 = resident capacity).  Results do not depend on it. */
-int wcc2d_set_launch(wcc2d_ctx* c, int threads_per_block, int blocks);
+/* Launch shape: threads per block (64..256, multiple of 64; 0 = 256),
+ * blocks per launch (0 = resident capacity) and the work decomposition
+ * (variant 0: every wavefront expands 8 x 8 old-cell tiles and produces their
+ * 7 x 7 new cells; 1: wavefronts walk 64-column strips upward one row at a
+ * time, expanding every old cell once per strip; 2, the default: as 1, with
+ * the next row's loads issued before the current row is expanded; -1 keeps
+ * the current one).  Results do not depend on it.  Errors: WCC_EINVAL. */
+int wcc2d_set_launch(wcc2d_ctx* c, int threads_per_block, int blocks, int variant);
 
 /* Milliseconds between the HIP events around the last wcc2d_run. */
 int wcc2d_last_run_ms(wcc2d_ctx* c, double* ms);

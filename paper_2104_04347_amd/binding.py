@@ -104,7 +104,7 @@ SIGNATURES = {
     "wcc2d_run": ([_vp, _i64, _c.c_double], _c.c_int),
     "wcc2d_advance": ([_vp, _c.c_double, _c.c_double, _i64, _c.POINTER(_i64)], _c.c_int),
     "wcc2d_read_dofs": ([_vp, _dp, _i64, _c.POINTER(wcc2d_state_info)], _c.c_int),
-    "wcc2d_set_launch": ([_vp, _c.c_int, _c.c_int], _c.c_int),
+    "wcc2d_set_launch": ([_vp, _c.c_int, _c.c_int, _c.c_int], _c.c_int),
     "wcc2d_last_run_ms": ([_vp, _dp], _c.c_int),
     "wcc2d_last_error": ([_vp], _c.c_char_p),
     "wcc2d_destroy": ([_vp], None),
@@ -403,8 +403,9 @@ class Solver2D:
                two_d=True)
         return q, inf
 
-    def set_launch(self, threads: int = 0, blocks: int = 0) -> None:
-        _check(load().wcc2d_set_launch(self.h, int(threads), int(blocks)), "wcc2d_set_launch", self.h, two_d=True)
+    def set_launch(self, threads: int = 0, blocks: int = 0, variant: int = -1) -> None:
+        _check(load().wcc2d_set_launch(self.h, int(threads), int(blocks), int(variant)), "wcc2d_set_launch", self.h,
+               two_d=True)
 
     def last_run_ms(self) -> float:
         ms = ctypes.c_double()

@@ -47,6 +47,7 @@ struct wcc2d_ctx {
   int parity_w = 0;
   int64_t launched = 0, steps = 0;
   int threads = 256, blocks = 0, cu = 0;
+  int variant = 2;   // 0: 8 x 8 wave tiles, 1: row marching over 64-column strips, 2: the same with prefetch
   hipStream_t capture = nullptr;
   hipGraphExec_t graphs[6] = {};
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -103,18 +104,20 @@ Step2Args args_for(const wcc2d_ctx* c, int parity, int slot, double dt_fixed) {
 
 int blocks_for(wcc2d_ctx* c) {
   if (c->blocks > 0) return c->blocks;
-  const int64_t tiles = ((c->Nx + 6) / 7) * ((c->Ny + 6) / 7);
+  // work units: 8 x 8 tiles (variant 0) or rows of 64-column strips
+  const int64_t units = c->variant >= 1 ? ((c->Nx + 62) / 63) * c->Ny : ((c->Nx + 6) / 7) * ((c->Ny + 6) / 7);
   const int waves = c->threads / 64;
   int per_cu = 0;
-  if (wcc2d::occupancy_half_step2(c->eq, c->P, c->prm.limiter != 0, c->threads, &per_cu) != hipSuccess || per_cu < 1)
+  if (wcc2d::occupancy_half_step2(c->eq, c->P, c->prm.limiter != 0, c->variant, c->threads, &per_cu) != hipSuccess ||
+      per_cu < 1)
     per_cu = 1;
-  const int64_t full = (int64_t)per_cu * c->cu, need = (tiles + waves - 1) / waves;
+  const int64_t full = (int64_t)per_cu * c->cu, need = (units + waves - 1) / waves;
   return (int)std::max<int64_t>(1, std::min(full, need));
 }
 
 int enqueue2(wcc2d_ctx* c, int parity, int slot, double dt_fixed, hipStream_t s) {
   hipError_t e = wcc2d::launch_half_step2(args_for(c, parity, slot, dt_fixed), c->eq, c->P, c->prm.limiter != 0,
-                                          blocks_for(c), c->threads, s);
+                                          c->variant, blocks_for(c), c->threads, s);
   if (e != hipSuccess) return fail2(c, WCC_EDEVICE, "2D half-step launch: %s", hipGetErrorString(e));
   return WCC_OK;
 }
@@ -407,13 +410,15 @@ int wcc2d_read_dofs(wcc2d_ctx* c, double* host, int64_t cap, wcc2d_state_info* i
   return WCC_OK;
 }
 
-int wcc2d_set_launch(wcc2d_ctx* c, int threads_per_block, int blocks) {
+int wcc2d_set_launch(wcc2d_ctx* c, int threads_per_block, int blocks, int variant) {
   if (!c) return WCC_EINVAL;
+  if (variant < -1 || variant > 2) return fail2(c, WCC_EINVAL, "variant must be -1 (keep), 0, 1 or 2");
   if (threads_per_block != 0 && (threads_per_block % 64 != 0 || threads_per_block < 64 || threads_per_block > 256))
     return fail2(c, WCC_EINVAL, "threads per block must be 64, 128, 192 or 256");
   if (blocks < 0) return fail2(c, WCC_EINVAL, "negative block count");
   c->threads = threads_per_block ? threads_per_block : 256;
   c->blocks = blocks;
+  if (variant >= 0) c->variant = variant;
   drop_graphs(c);
   return WCC_OK;
 }

@@ -25,8 +25,11 @@ struct Step2Args {
   unsigned long long* parts;
 };
 
-hipError_t launch_half_step2(const Step2Args& a, int eq, int P, bool lim, int blocks, int threads, hipStream_t s);
+// variant 0: 8 x 8 wave tiles; 1: row marching over 64-column strips; 2: the
+// same with the next row prefetched (identical results)
+hipError_t launch_half_step2(const Step2Args& a, int eq, int P, bool lim, int variant, int blocks, int threads,
+                             hipStream_t s);
 hipError_t launch_state_speed2(const Step2Args& a, int eq, int P, int blocks, hipStream_t s);
-hipError_t occupancy_half_step2(int eq, int P, bool lim, int threads, int* blocks_per_cu);
+hipError_t occupancy_half_step2(int eq, int P, bool lim, int variant, int threads, int* blocks_per_cu);
 
 }  // namespace wcc2d

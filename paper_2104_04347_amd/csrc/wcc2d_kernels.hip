@@ -1,18 +1,13 @@
 // wcc2d_kernels.hip -- the fused 2D half-step kernel for gfx950 (Section 3,
 // Appendix B; the 2D Euler step of Section 4).
 //
-// Work decomposition:
-//   * a wavefront owns an 8 x 8 tile of OLD cells (lane = 8*ly + lx) and
-//     produces the 7 x 7 NEW cells whose four parents all lie in the tile;
-//     every lane expands its own old cell in registers;
-//   * the parents of the new cell at (lx, ly) are the old cells at lanes
-//     l (lower-left), l+8 (upper-left), l+1 (lower-right), l+9 (upper-right):
-//     their interface quantities arrive by wave shuffles, one component at a
-//     time;
-//   * blocks own contiguous ranges of tiles (row-major over the tile grid);
-//   * the time step comes from the same device-side ring as the 1D kernels
-//     (dt = cfl / smax with smax the largest s_x/dx + s_y/dy of the previous
-//     step's new averages), reduced through 64 partial slots.
+// Two work decompositions with identical results (the launch variant):
+// 8 x 8 wave tiles exchanged by shuffles, and 64-column strips walked row by
+// row with a one-row carry in LDS, with or without prefetch of the next row
+// (described at each kernel).  The time step
+// comes from the same device-side ring as the 1D kernels (dt = cfl / smax
+// with smax the largest s_x/dx + s_y/dy of the previous step's new
+// averages), reduced through 64 partial slots.
 #include <hip/hip_runtime.h>
 
 #include "wcc2d_cell.hpp"
@@ -21,10 +16,11 @@
 
 namespace wcc2d {
 
-// periodic index of an old cell; a tile reaches one cell before 0 and seven
-// past its first cell, so one wrap suffices unless the mesh is narrower than 8
+// periodic index of an old cell; a tile or strip reaches one cell before 0
+// and at most 63 past its first cell, so one wrap suffices unless the mesh is
+// narrower than 64
 __device__ __forceinline__ int wrap(int i, int n) {
-  if (n >= 8) {
+  if (n >= 64) {
     if (i < 0) return i + n;
     if (i >= n) return i - n;
     return i;
@@ -33,26 +29,51 @@ __device__ __forceinline__ int wrap(int i, int n) {
   return r < 0 ? r + n : r;
 }
 
-template <int EQ, int P, bool LIM>
-__device__ __forceinline__ void run_tile2(const Step2Args& a, int tile, int tiles_x, double nlx, double nly,
-                                          double hx, double hy, int lane, double& smax, unsigned& flags) {
-  constexpr int NC = ncomp<EQ>(), ND = ndof(P), NV = nvert(P) > 0 ? nvert(P) : 1;
-  const int tx = tile % tiles_x, ty = tile / tiles_x;
-  const int lx = lane & 7, ly = lane >> 3;
-  const int off = a.parity_old == 0 ? 0 : -1;
-  const int i = wrap(7 * tx + lx + off, a.Nx), j = wrap(7 * ty + ly + off, a.Ny);
-  const uint32_t cell = (uint32_t)(j * a.Nx + i);
-  double q[NC][ND];
-#pragma unroll
-  for (int c = 0; c < NC; ++c)
-#pragma unroll
-    for (int d = 0; d < ND; ++d) q[c][d] = wcc::row_at(wcc::row_base(a.q_old + (int64_t)(c * ND + d) * a.plane), cell);
-  Old2<EQ, P> o;
-  old_cell2<EQ, P>(q, nlx, nly, a.ph, o);
+// One component's parent data at a lane, as the new cell uses it: the
+// quarter-average sum h and the flux differences fx, gy of Eq. 2DIntegral
+// (grouped as the oracle groups them) and the vertex values of the four
+// parents, A lower-left, B upper-left, C lower-right, E upper-right.
+template <int P>
+struct Par2 {
+  static constexpr int NV = nvert(P) > 0 ? nvert(P) : 1;
+  double h, fx, gy;
+  double VA[NV], VB[NV], VC[NV], VE[NV];
+};
 
-  const int ni = 7 * tx + lx, nj = 7 * ty + ly;
-  const bool mine = lx < 7 && ly < 7 && ni < a.Nx && nj < a.Ny;
-  const uint32_t ncell = (uint32_t)(nj * a.Nx + ni);
+template <int P>
+__device__ __forceinline__ void combine(Par2<P>& g, double A_RU, double B_RD, double C_LU, double E_LD, double A_fU,
+                                        double C_fU, double B_fD, double E_fD, double A_gR, double B_gR,
+                                        double C_gL, double E_gL) {
+  g.h = 0.25 * (((A_RU + B_RD) + C_LU) + E_LD);
+  g.fx = (A_fU - C_fU) + (B_fD - E_fD);
+  g.gy = (A_gR - B_gR) + (C_gL - E_gL);
+}
+
+template <int EQ, int P>
+__device__ __forceinline__ void store_cell(const Step2Args& a, int c, uint32_t ncell, double pv,
+                                           const double (&D)[P + 1][P + 1], unsigned& flags) {
+  constexpr int ND = ndof(P);
+  bool ok = __builtin_isfinite(pv);
+  wcc::row_store(wcc::row_base(a.q_new + (int64_t)(c * ND) * a.plane), ncell, pv);
+#pragma unroll
+  for (int n = 1; n <= P; ++n)
+#pragma unroll
+    for (int l = 0; l <= n; ++l) {
+      const double x = D[n - l][l];
+      ok = ok && __builtin_isfinite(x);
+      wcc::row_store(wcc::row_base(a.q_new + (int64_t)(c * ND + dof(n - l, l)) * a.plane), ncell, x);
+    }
+  if (!ok) flags |= 1u;
+}
+
+// New cell of this lane from its parents' data (gather(c, g) fills Par2 for
+// component c): average (Eq. 2DIntegral), derivatives (Eq. 2DDerivatives),
+// limiter (Section 3.2; characteristic fields for Euler, Section 4), point
+// value, store, wave-speed rate.
+template <int EQ, int P, bool LIM, class Gather>
+__device__ __forceinline__ void new_cell2(const Step2Args& a, Gather&& gather, bool mine, uint32_t ncell, double hx,
+                                          double hy, double& smax, unsigned& flags) {
+  constexpr int NC = ncomp<EQ>();
   double ab[NC];
   if constexpr (EQ == kEuler && LIM && P >= 1) {
     // the characteristic limiter couples the components: form all four new
@@ -60,94 +81,94 @@ __device__ __forceinline__ void run_tile2(const Step2Args& a, int tile, int tile
     double D[4][P + 1][P + 1], vx[4][4];
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
-      const double B_RD = __shfl(o.RD[c], lane + 8, 64), B_fD = __shfl(o.fD[c], lane + 8, 64),
-                   B_gR = __shfl(o.gR[c], lane + 8, 64);
-      const double C_LU = __shfl(o.LU[c], lane + 1, 64), C_fU = __shfl(o.fU[c], lane + 1, 64),
-                   C_gL = __shfl(o.gL[c], lane + 1, 64);
-      const double E_LD = __shfl(o.LD[c], lane + 9, 64), E_fD = __shfl(o.fD[c], lane + 9, 64),
-                   E_gL = __shfl(o.gL[c], lane + 9, 64);
-      double VB[NV], VC[NV], VE[NV];
-#pragma unroll
-      for (int d = 0; d < NV; ++d) {
-        VB[d] = __shfl(o.V[c][d], lane + 8, 64);
-        VC[d] = __shfl(o.V[c][d], lane + 1, 64);
-        VE[d] = __shfl(o.V[c][d], lane + 9, 64);
-      }
-      const double h = 0.25 * (((o.RU[c] + B_RD) + C_LU) + E_LD);
-      const double fx = (o.fU[c] - C_fU) + (B_fD - E_fD);
-      const double gy = (o.gR[c] - B_gR) + (C_gL - E_gL);
-      ab[c] = __builtin_fma(hy, gy, __builtin_fma(hx, fx, h));
-      new_derivatives<P>(o.V[c], VB, VC, VE, D[c]);
-      vx[c][0] = o.V[c][0];
-      vx[c][1] = VC[0];
-      vx[c][2] = VE[0];
-      vx[c][3] = VB[0];
+      Par2<P> g;
+      gather(c, g);
+      ab[c] = __builtin_fma(hy, g.gy, __builtin_fma(hx, g.fx, g.h));
+      new_derivatives<P>(g.VA, g.VB, g.VC, g.VE, D[c]);
+      vx[c][0] = g.VA[0];
+      vx[c][1] = g.VC[0];
+      vx[c][2] = g.VE[0];
+      vx[c][3] = g.VB[0];
     }
     char_limit2d<P>(a.ph, a.dx, a.dy, ab, D, vx);
     if (mine) {
 #pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        const double pv = point_value<P>(ab[c], D[c]);
-        bool ok = __builtin_isfinite(pv);
-        wcc::row_store(wcc::row_base(a.q_new + (int64_t)(c * ND) * a.plane), ncell, pv);
-#pragma unroll
-        for (int n = 1; n <= P; ++n)
-#pragma unroll
-          for (int l = 0; l <= n; ++l) {
-            const double x = D[c][n - l][l];
-            ok = ok && __builtin_isfinite(x);
-            wcc::row_store(wcc::row_base(a.q_new + (int64_t)(c * ND + dof(n - l, l)) * a.plane), ncell, x);
-          }
-        if (!ok) flags |= 1u;
-      }
+      for (int c = 0; c < 4; ++c) store_cell<EQ, P>(a, c, ncell, point_value<P>(ab[c], D[c]), D[c], flags);
     }
   } else {
 #pragma unroll
-  for (int c = 0; c < NC; ++c) {
-    // right / upper parents' halves of this component
-    const double B_RD = __shfl(o.RD[c], lane + 8, 64), B_fD = __shfl(o.fD[c], lane + 8, 64),
-                 B_gR = __shfl(o.gR[c], lane + 8, 64);
-    const double C_LU = __shfl(o.LU[c], lane + 1, 64), C_fU = __shfl(o.fU[c], lane + 1, 64),
-                 C_gL = __shfl(o.gL[c], lane + 1, 64);
-    const double E_LD = __shfl(o.LD[c], lane + 9, 64), E_fD = __shfl(o.fD[c], lane + 9, 64),
-                 E_gL = __shfl(o.gL[c], lane + 9, 64);
-    double VB[NV], VC[NV], VE[NV];
-#pragma unroll
-    for (int d = 0; d < NV; ++d) {
-      VB[d] = __shfl(o.V[c][d], lane + 8, 64);
-      VC[d] = __shfl(o.V[c][d], lane + 1, 64);
-      VE[d] = __shfl(o.V[c][d], lane + 9, 64);
+    for (int c = 0; c < NC; ++c) {
+      Par2<P> g;
+      gather(c, g);
+      const double abar = __builtin_fma(hy, g.gy, __builtin_fma(hx, g.fx, g.h));
+      ab[c] = abar;
+      double D[P + 1][P + 1];
+      if constexpr (P >= 1) new_derivatives<P>(g.VA, g.VB, g.VC, g.VE, D);
+      if constexpr (LIM && P >= 1) limit2d<P>(a.ph.eps, abar, D, g.VA[0], g.VC[0], g.VE[0], g.VB[0]);
+      const double pv = point_value<P>(abar, D);
+      if (mine) store_cell<EQ, P>(a, c, ncell, pv, D, flags);
     }
-    // Eq. 2DIntegral
-    const double h = 0.25 * (((o.RU[c] + B_RD) + C_LU) + E_LD);
-    const double fx = (o.fU[c] - C_fU) + (B_fD - E_fD);
-    const double gy = (o.gR[c] - B_gR) + (C_gL - E_gL);
-    const double abar = __builtin_fma(hy, gy, __builtin_fma(hx, fx, h));
-    ab[c] = abar;
-    double D[P + 1][P + 1];
-    if constexpr (P >= 1) new_derivatives<P>(o.V[c], VB, VC, VE, D);
-    if constexpr (LIM && P >= 1) limit2d<P>(a.ph.eps, abar, D, o.V[c][0], VC[0], VE[0], VB[0]);
-    const double pv = point_value<P>(abar, D);
-    if (mine) {
-      bool ok = __builtin_isfinite(pv);
-      wcc::row_store(wcc::row_base(a.q_new + (int64_t)(c * ND) * a.plane), ncell, pv);
-#pragma unroll
-      for (int n = 1; n <= P; ++n)
-#pragma unroll
-        for (int l = 0; l <= n; ++l) {
-          const double x = D[n - l][l];
-          ok = ok && __builtin_isfinite(x);
-          wcc::row_store(wcc::row_base(a.q_new + (int64_t)(c * ND + dof(n - l, l)) * a.plane), ncell, x);
-        }
-      if (!ok) flags |= 1u;
-    }
-  }
   }
   if (mine) {
     const double sr = speed_rate<EQ>(ab, a.ph, a.idx, a.idy, flags);
     if (!__builtin_isfinite(sr)) flags |= 1u;
     smax = __builtin_fmax(smax, sr);
   }
+}
+
+// Load the state of the old cell (i, j) of this lane.
+template <int EQ, int P>
+__device__ __forceinline__ void load_old(const Step2Args& a, int i, int j, double (&q)[ncomp<EQ>()][ndof(P)]) {
+  constexpr int NC = ncomp<EQ>(), ND = ndof(P);
+  const uint32_t cell = (uint32_t)(j * a.Nx + i);
+#pragma unroll
+  for (int c = 0; c < NC; ++c)
+#pragma unroll
+    for (int d = 0; d < ND; ++d) q[c][d] = wcc::row_at(wcc::row_base(a.q_old + (int64_t)(c * ND + d) * a.plane), cell);
+}
+
+// Load and expand the old cell (i, j) of this lane.
+template <int EQ, int P>
+__device__ __forceinline__ void old_of(const Step2Args& a, int i, int j, double nlx, double nly, Old2<EQ, P>& o) {
+  double q[ncomp<EQ>()][ndof(P)];
+  load_old<EQ, P>(a, i, j, q);
+  old_cell2<EQ, P>(q, nlx, nly, a.ph, o);
+}
+
+// ---- variant 0: 8 x 8 wave tiles ------------------------------------------
+// A wavefront owns an 8 x 8 tile of old cells (lane = 8*ly + lx) and
+// produces the 7 x 7 new cells whose four parents lie in the tile; the
+// parents of the new cell at (lx, ly) are the old cells at lanes l (A),
+// l+8 (B), l+1 (C), l+9 (E), exchanged by wave shuffles.  Blocks own
+// contiguous ranges of tiles (row-major over the tile grid).
+template <int EQ, int P, bool LIM>
+__device__ __forceinline__ void run_tile2(const Step2Args& a, int tile, int tiles_x, double nlx, double nly,
+                                          double hx, double hy, int lane, double& smax, unsigned& flags) {
+  constexpr int NV = Par2<P>::NV;
+  const int tx = tile % tiles_x, ty = tile / tiles_x;
+  const int lx = lane & 7, ly = lane >> 3;
+  const int off = a.parity_old == 0 ? 0 : -1;
+  Old2<EQ, P> o;
+  old_of<EQ, P>(a, wrap(7 * tx + lx + off, a.Nx), wrap(7 * ty + ly + off, a.Ny), nlx, nly, o);
+  const int ni = 7 * tx + lx, nj = 7 * ty + ly;
+  const bool mine = lx < 7 && ly < 7 && ni < a.Nx && nj < a.Ny;
+  auto gather = [&](int c, Par2<P>& g) {
+    const double B_RD = __shfl(o.RD[c], lane + 8, 64), B_fD = __shfl(o.fD[c], lane + 8, 64),
+                 B_gR = __shfl(o.gR[c], lane + 8, 64);
+    const double C_LU = __shfl(o.LU[c], lane + 1, 64), C_fU = __shfl(o.fU[c], lane + 1, 64),
+                 C_gL = __shfl(o.gL[c], lane + 1, 64);
+    const double E_LD = __shfl(o.LD[c], lane + 9, 64), E_fD = __shfl(o.fD[c], lane + 9, 64),
+                 E_gL = __shfl(o.gL[c], lane + 9, 64);
+#pragma unroll
+    for (int d = 0; d < NV; ++d) {
+      g.VA[d] = o.V[c][d];
+      g.VB[d] = __shfl(o.V[c][d], lane + 8, 64);
+      g.VC[d] = __shfl(o.V[c][d], lane + 1, 64);
+      g.VE[d] = __shfl(o.V[c][d], lane + 9, 64);
+    }
+    combine<P>(g, o.RU[c], B_RD, C_LU, E_LD, o.fU[c], C_fU, B_fD, E_fD, o.gR[c], B_gR, C_gL, E_gL);
+  };
+  new_cell2<EQ, P, LIM>(a, gather, mine, (uint32_t)(nj * a.Nx + ni), hx, hy, smax, flags);
 }
 
 template <int EQ, int P, bool LIM>
@@ -168,6 +189,112 @@ __global__ __launch_bounds__(256) void k2d_half_step(const Step2Args a) {
   unsigned flags = 0u;
   for (int tile = t_begin + wave; tile < t_stop; tile += nw)
     run_tile2<EQ, P, LIM>(a, tile, tiles_x, nlx, nly, hx, hy, lane, smax, flags);
+  wcc::publish(a.ctrl, a.parts, a.slot, smax, flags);
+}
+
+// ---- variant 1: row marching -----------------------------------------------
+// The mesh is cut into strips of 64 old columns (63 new columns each; the
+// 64th old column holds the right parents of the 63rd new one).  A wavefront
+// walks a contiguous run of (strip, row) units, strip-major, one mesh row at
+// a time, lane = column in the strip.  At unit (strip, r) it expands the old
+// row above new row r: the lane's old cell is the upper-left parent B of its
+// new cell and the next lane's the upper-right parent E (DPP shift by one
+// lane); the lower parents A and C are the previous row's expansion, kept by
+// each lane in its own LDS slot (C again from the next lane).  Every old cell
+// is expanded once per strip -- plus one extra row where a run starts or
+// enters a new strip -- and every row is loaded and stored 64 cells wide.
+template <int EQ, int P>
+struct RowCarry {
+  static constexpr int NQ = 5 + nvert(P);   // RU, LU, fU, gR, gL, V[0..nvert)
+  double v[ncomp<EQ>()][NQ][64];
+};
+
+template <int EQ, int P>
+__device__ __forceinline__ void put_carry(RowCarry<EQ, P>& carry, int c, int lane, const Old2<EQ, P>& o) {
+  carry.v[c][0][lane] = o.RU[c];
+  carry.v[c][1][lane] = o.LU[c];
+  carry.v[c][2][lane] = o.fU[c];
+  carry.v[c][3][lane] = o.gR[c];
+  carry.v[c][4][lane] = o.gL[c];
+#pragma unroll
+  for (int d = 0; d < nvert(P); ++d) carry.v[c][5 + d][lane] = o.V[c][d];
+}
+
+// PF: load the next unit's upper row before expanding the current one (one
+// row of state in flight per wave, at the cost of its registers).
+template <int EQ, int P, bool LIM, bool PF>
+__global__ __launch_bounds__(256) void k2d_half_step_rows(const Step2Args a) {
+  constexpr int NC = ncomp<EQ>(), NV = nvert(P), ND = ndof(P);
+  __shared__ RowCarry<EQ, P> carry_all[4];
+  const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6),
+            nw = blockDim.x >> 6;
+  RowCarry<EQ, P>& carry = carry_all[wave];
+  const int strips = (a.Nx + 62) / 63, rows = a.Ny;
+  const int64_t units = (int64_t)strips * rows, waves = (int64_t)gridDim.x * nw;
+  const int64_t gw = (int64_t)blockIdx.x * nw + wave;
+  const int u_begin = (int)(gw * units / waves), u_end = (int)((gw + 1) * units / waves);
+  double dt;
+  if (!wcc::step_time(a.ctrl, a.parts, a.slot, 1.0, a.dt_fixed, blockIdx.x == 0 && threadIdx.x < 64, dt)) return;
+  const double lamx = dt / a.dx, lamy = dt / a.dy;
+  const double nlx = -lamx, nly = -lamy, hx = 0.5 * lamx, hy = 0.5 * lamy;
+  const int off = a.parity_old == 0 ? 0 : -1;
+  double smax = 0.0;
+  unsigned flags = 0u;
+  double qn[NC][ND];
+  if (PF && u_begin < u_end) {
+    const int sx = u_begin / rows, r = u_begin - sx * rows;
+    load_old<EQ, P>(a, wrap(63 * sx + lane + off, a.Nx), wrap(r + 1 + off, a.Ny), qn);
+  }
+  for (int u = u_begin; u < u_end; ++u) {
+    const int sx = u / rows, r = u - sx * rows;
+    const int i = wrap(63 * sx + lane + off, a.Nx);
+    if (u == u_begin || r == 0) {
+      // lower parents of new row r: the old row below, expanded afresh
+      Old2<EQ, P> o;
+      old_of<EQ, P>(a, i, wrap(r + off, a.Ny), nlx, nly, o);
+#pragma unroll
+      for (int c = 0; c < NC; ++c) put_carry<EQ, P>(carry, c, lane, o);
+    }
+    double q[NC][ND];
+    if constexpr (PF) {
+#pragma unroll
+      for (int c = 0; c < NC; ++c)
+#pragma unroll
+        for (int d = 0; d < ND; ++d) q[c][d] = qn[c][d];
+      if (u + 1 < u_end) {
+        const int sx2 = (u + 1) / rows, r2 = u + 1 - sx2 * rows;
+        load_old<EQ, P>(a, wrap(63 * sx2 + lane + off, a.Nx), wrap(r2 + 1 + off, a.Ny), qn);
+      }
+      __builtin_amdgcn_sched_barrier(0);
+    } else {
+      load_old<EQ, P>(a, i, wrap(r + 1 + off, a.Ny), q);
+    }
+    Old2<EQ, P> o;
+    old_cell2<EQ, P>(q, nlx, nly, a.ph, o);
+    const int ni = 63 * sx + lane;
+    const bool mine = lane < 63 && ni < a.Nx;
+    auto gather = [&](int c, Par2<P>& g) {
+      // the lane's own slot: read the row below, then leave this row for the
+      // next unit
+      const double A_RU = carry.v[c][0][lane], A_LU = carry.v[c][1][lane], A_fU = carry.v[c][2][lane],
+                   A_gR = carry.v[c][3][lane], A_gL = carry.v[c][4][lane];
+#pragma unroll
+      for (int d = 0; d < NV; ++d) g.VA[d] = carry.v[c][5 + d][lane];
+      put_carry<EQ, P>(carry, c, lane, o);
+      const double C_LU = wcc::dpp_from_next(A_LU), C_fU = wcc::dpp_from_next(A_fU),
+                   C_gL = wcc::dpp_from_next(A_gL);
+      const double E_LD = wcc::dpp_from_next(o.LD[c]), E_fD = wcc::dpp_from_next(o.fD[c]),
+                   E_gL = wcc::dpp_from_next(o.gL[c]);
+#pragma unroll
+      for (int d = 0; d < NV; ++d) {
+        g.VB[d] = o.V[c][d];
+        g.VC[d] = wcc::dpp_from_next(g.VA[d]);
+        g.VE[d] = wcc::dpp_from_next(o.V[c][d]);
+      }
+      combine<P>(g, A_RU, o.RD[c], C_LU, E_LD, A_fU, C_fU, o.fD[c], E_fD, A_gR, o.gR[c], C_gL, E_gL);
+    };
+    new_cell2<EQ, P, LIM>(a, gather, mine, (uint32_t)(r * a.Nx + ni), hx, hy, smax, flags);
+  }
   wcc::publish(a.ctrl, a.parts, a.slot, smax, flags);
 }
 
@@ -203,31 +330,41 @@ __global__ __launch_bounds__(256) void k2d_state_speed(const Step2Args a) {
   wcc::publish(a.ctrl, a.parts, a.slot == 0 ? 2 : a.slot - 1, smax, flags);
 }
 
-template <int EQ, int P>
-static hipError_t launch_ep(const Step2Args& a, bool lim, int blocks, int threads, hipStream_t s) {
-  if (lim)
-    hipLaunchKernelGGL((k2d_half_step<EQ, P, true>), dim3(blocks), dim3(threads), 0, s, a);
+template <int EQ, int P, bool LIM>
+static hipError_t launch_epl(const Step2Args& a, int variant, int blocks, int threads, hipStream_t s) {
+  if (variant == 2)
+    hipLaunchKernelGGL((k2d_half_step_rows<EQ, P, LIM, true>), dim3(blocks), dim3(threads), 0, s, a);
+  else if (variant == 1)
+    hipLaunchKernelGGL((k2d_half_step_rows<EQ, P, LIM, false>), dim3(blocks), dim3(threads), 0, s, a);
   else
-    hipLaunchKernelGGL((k2d_half_step<EQ, P, false>), dim3(blocks), dim3(threads), 0, s, a);
+    hipLaunchKernelGGL((k2d_half_step<EQ, P, LIM>), dim3(blocks), dim3(threads), 0, s, a);
   return hipGetLastError();
 }
 
+template <int EQ, int P>
+static hipError_t launch_ep(const Step2Args& a, bool lim, int variant, int blocks, int threads, hipStream_t s) {
+  if (lim) return launch_epl<EQ, P, true>(a, variant, blocks, threads, s);
+  return launch_epl<EQ, P, false>(a, variant, blocks, threads, s);
+}
+
 template <int EQ>
-static hipError_t launch_e(const Step2Args& a, int P, bool lim, int blocks, int threads, hipStream_t s) {
+static hipError_t launch_e(const Step2Args& a, int P, bool lim, int variant, int blocks, int threads,
+                           hipStream_t s) {
   switch (P) {
-    case 0: return launch_ep<EQ, 0>(a, lim, blocks, threads, s);
-    case 1: return launch_ep<EQ, 1>(a, lim, blocks, threads, s);
-    case 2: return launch_ep<EQ, 2>(a, lim, blocks, threads, s);
-    case 3: return launch_ep<EQ, 3>(a, lim, blocks, threads, s);
+    case 0: return launch_ep<EQ, 0>(a, lim, variant, blocks, threads, s);
+    case 1: return launch_ep<EQ, 1>(a, lim, variant, blocks, threads, s);
+    case 2: return launch_ep<EQ, 2>(a, lim, variant, blocks, threads, s);
+    case 3: return launch_ep<EQ, 3>(a, lim, variant, blocks, threads, s);
   }
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_half_step2(const Step2Args& a, int eq, int P, bool lim, int blocks, int threads, hipStream_t s) {
+hipError_t launch_half_step2(const Step2Args& a, int eq, int P, bool lim, int variant, int blocks, int threads,
+                             hipStream_t s) {
   switch (eq) {
-    case kAdvection: return launch_e<kAdvection>(a, P, lim, blocks, threads, s);
-    case kBurgers: return launch_e<kBurgers>(a, P, lim, blocks, threads, s);
-    case kEuler: return launch_e<kEuler>(a, P, lim, blocks, threads, s);
+    case kAdvection: return launch_e<kAdvection>(a, P, lim, variant, blocks, threads, s);
+    case kBurgers: return launch_e<kBurgers>(a, P, lim, variant, blocks, threads, s);
+    case kEuler: return launch_e<kEuler>(a, P, lim, variant, blocks, threads, s);
   }
   return hipErrorInvalidValue;
 }
@@ -253,29 +390,37 @@ hipError_t launch_state_speed2(const Step2Args& a, int eq, int P, int blocks, hi
   return hipErrorInvalidValue;
 }
 
+template <int EQ, int P, bool LIM>
+static hipError_t occ_epl(int variant, int threads, int* per_cu) {
+  if (variant == 2)
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k2d_half_step_rows<EQ, P, LIM, true>, threads, 0);
+  if (variant == 1)
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k2d_half_step_rows<EQ, P, LIM, false>, threads, 0);
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k2d_half_step<EQ, P, LIM>, threads, 0);
+}
+
 template <int EQ, int P>
-static hipError_t occ_ep(bool lim, int threads, int* per_cu) {
-  if (lim)
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k2d_half_step<EQ, P, true>, threads, 0);
-  return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k2d_half_step<EQ, P, false>, threads, 0);
+static hipError_t occ_ep(bool lim, int variant, int threads, int* per_cu) {
+  if (lim) return occ_epl<EQ, P, true>(variant, threads, per_cu);
+  return occ_epl<EQ, P, false>(variant, threads, per_cu);
 }
 
 template <int EQ>
-static hipError_t occ_e(int P, bool lim, int threads, int* per_cu) {
+static hipError_t occ_e(int P, bool lim, int variant, int threads, int* per_cu) {
   switch (P) {
-    case 0: return occ_ep<EQ, 0>(lim, threads, per_cu);
-    case 1: return occ_ep<EQ, 1>(lim, threads, per_cu);
-    case 2: return occ_ep<EQ, 2>(lim, threads, per_cu);
-    case 3: return occ_ep<EQ, 3>(lim, threads, per_cu);
+    case 0: return occ_ep<EQ, 0>(lim, variant, threads, per_cu);
+    case 1: return occ_ep<EQ, 1>(lim, variant, threads, per_cu);
+    case 2: return occ_ep<EQ, 2>(lim, variant, threads, per_cu);
+    case 3: return occ_ep<EQ, 3>(lim, variant, threads, per_cu);
   }
   return hipErrorInvalidValue;
 }
 
-hipError_t occupancy_half_step2(int eq, int P, bool lim, int threads, int* per_cu) {
+hipError_t occupancy_half_step2(int eq, int P, bool lim, int variant, int threads, int* per_cu) {
   switch (eq) {
-    case kAdvection: return occ_e<kAdvection>(P, lim, threads, per_cu);
-    case kBurgers: return occ_e<kBurgers>(P, lim, threads, per_cu);
-    case kEuler: return occ_e<kEuler>(P, lim, threads, per_cu);
+    case kAdvection: return occ_e<kAdvection>(P, lim, variant, threads, per_cu);
+    case kBurgers: return occ_e<kBurgers>(P, lim, variant, threads, per_cu);
+    case kEuler: return occ_e<kEuler>(P, lim, variant, threads, per_cu);
   }
   return hipErrorInvalidValue;
 }

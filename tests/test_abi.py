@@ -118,5 +118,7 @@ def test_2d_create_validates():
     assert nb.value >= 2 * 4 * 10 * plane * 8            # two buffers of 4 components x 10 DOFs
     assert lib.wcc2d_step(h, ctypes.c_double(0.25), ctypes.c_double(0.0)) == binding.WCC_ESTATE
     assert lib.wcc2d_bind(h, ctypes.c_void_p(256), 16, None) == binding.WCC_ESIZE
-    assert lib.wcc2d_set_launch(h, 100, 0) == binding.WCC_EINVAL
+    assert lib.wcc2d_set_launch(h, 100, 0, -1) == binding.WCC_EINVAL
+    assert lib.wcc2d_set_launch(h, 0, 0, 3) == binding.WCC_EINVAL
+    assert lib.wcc2d_set_launch(h, 128, 0, 0) == 0
     lib.wcc2d_destroy(h)

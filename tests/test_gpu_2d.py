@@ -1,6 +1,7 @@
 """GPU parity of the 2D half-step (Section 3, Appendix B; 2D Euler, Section 4)
 against the 2D oracle: bit for bit (binary64, the same written operation
-order on both sides), on ragged tile edges, meshes narrower than a tile,
+order on both sides), for both work decompositions (8 x 8 wave tiles and
+row marching over 64-column strips) and several launch shapes, on ragged tile edges, meshes narrower than a tile,
 graph-replayed runs and the Euler vortex of Table 3, unlimited and with the
 rotated characteristic limiter."""
 import numpy as np
@@ -14,10 +15,11 @@ CFL = {0: 0.4, 1: 0.4, 2: 0.3, 3: 0.25}
 
 
 def gpu_run(eq, P, Nx, Ny, q0, limiter, dom=(0.0, 2.0, 0.0, 2.0), cfl=None, half_steps=None, t_end=None, a=0.7,
-            b=-0.4, dt_fixed=None):
+            b=-0.4, dt_fixed=None, variant=-1):
     s = binding.Solver2D(eq, P, Nx, Ny, limiter=limiter, x_left=dom[0], x_right=dom[1], y_left=dom[2],
                          y_right=dom[3], a=a, b=b)
     try:
+        s.set_launch(0, 0, variant)
         s.write(q0)
         if dt_fixed is not None:
             for _ in range(half_steps):
@@ -52,24 +54,48 @@ def modes_state(P, Nx, Ny, seed=3):
     return inputs.taylor2d(fn, P, Nx, Ny)
 
 
+VARIANTS = [0, 1, 2]   # 8 x 8 wave tiles; row marching over 64-column strips, without and with prefetch
+
+
+@pytest.mark.parametrize("variant", VARIANTS)
 @pytest.mark.parametrize("eq", ["advection", "burgers"])
 @pytest.mark.parametrize("P", [0, 1, 2, 3])
 @pytest.mark.parametrize("limiter", [False, True])
-def test_scalar_bitwise(eq, P, limiter):
-    Nx, Ny = 37, 29                       # ragged 7-cell tiles in both directions
+def test_scalar_bitwise(eq, P, limiter, variant):
+    Nx, Ny = 137, 29                      # ragged tiles and strips in both directions
     q0 = modes_state(P, Nx, Ny)
-    q, info = gpu_run(eq, P, Nx, Ny, q0, limiter, cfl=CFL[P], half_steps=30)
+    q, info = gpu_run(eq, P, Nx, Ny, q0, limiter, cfl=CFL[P], half_steps=30, variant=variant)
     r = oracle_run(eq, P, Nx, Ny, q0, limiter, cfl=CFL[P], half_steps=30)
-    assert_bitwise(q, info, r, f"{eq} P={P} lim={limiter}")
+    assert_bitwise(q, info, r, f"{eq} P={P} lim={limiter} variant={variant}")
 
 
-@pytest.mark.parametrize("Nx,Ny", [(2, 3), (5, 7), (8, 8), (9, 2), (15, 14)])
-def test_small_meshes_bitwise(Nx, Ny):
+@pytest.mark.parametrize("variant", VARIANTS)
+@pytest.mark.parametrize("Nx,Ny", [(2, 3), (5, 7), (8, 8), (9, 2), (15, 14), (16, 16), (31, 5), (2, 2)])
+def test_small_meshes_bitwise(Nx, Ny, variant):
     P = 3
     q0 = modes_state(P, Nx, Ny, seed=4)
-    q, info = gpu_run("burgers", P, Nx, Ny, q0, True, cfl=CFL[P], half_steps=9)
+    q, info = gpu_run("burgers", P, Nx, Ny, q0, True, cfl=CFL[P], half_steps=9, variant=variant)
     r = oracle_run("burgers", P, Nx, Ny, q0, True, cfl=CFL[P], half_steps=9)
-    assert_bitwise(q, info, r, f"Nx={Nx} Ny={Ny}")
+    assert_bitwise(q, info, r, f"Nx={Nx} Ny={Ny} variant={variant}")
+
+
+@pytest.mark.parametrize("variant", [1, 2])
+@pytest.mark.parametrize("threads,blocks", [(64, 1), (64, 3), (128, 7), (256, 2), (192, 0)])
+def test_strip_launch_shapes_bitwise(threads, blocks, variant):
+    """Row marching: runs of (strip, row) units split over 1 to 28 waves,
+    starting and ending inside strips, on a mesh of three ragged strips."""
+    P, Nx, Ny = 2, 150, 43
+    q0 = modes_state(P, Nx, Ny, seed=8)
+    s = binding.Solver2D("burgers", P, Nx, Ny, limiter=True, x_left=0.0, x_right=2.0, y_left=0.0, y_right=2.0)
+    try:
+        s.set_launch(threads, blocks, variant)
+        s.write(q0)
+        s.run(7, CFL[P])
+        q, info = s.read()
+    finally:
+        s.close()
+    r = oracle_run("burgers", P, Nx, Ny, q0, True, cfl=CFL[P], half_steps=7, a=1.0, b=1.0)
+    assert_bitwise(q, info, r, f"threads={threads} blocks={blocks} variant={variant}")
 
 
 def test_graph_replay_and_advance_bitwise():
@@ -95,31 +121,34 @@ def test_fixed_dt_bitwise():
     assert_bitwise(q, info, r, "fixed dt")
 
 
+@pytest.mark.parametrize("variant", VARIANTS)
 @pytest.mark.parametrize("P", [1, 2, 3])
-def test_euler_vortex_bitwise(P):
+def test_euler_vortex_bitwise(P, variant):
     """Table 3's setup (isentropic vortex, mesh 1/5, t = 2), unlimited."""
     N = 50
     q0 = inputs.isentropic_vortex(P, N)
     dom = (-5.0, 5.0, -5.0, 5.0)
-    q, info = gpu_run("euler", P, N, N, q0, False, dom=dom, cfl=CFL[P], t_end=2.0)
+    q, info = gpu_run("euler", P, N, N, q0, False, dom=dom, cfl=CFL[P], t_end=2.0, variant=variant)
     r = oracle_run("euler", P, N, N, q0, False, dom=dom, cfl=CFL[P], t_end=2.0)
     assert_bitwise(q, info, r, f"vortex P={P}")
 
 
+@pytest.mark.parametrize("variant", VARIANTS)
 @pytest.mark.parametrize("P", [1, 2, 3])
-def test_euler_vortex_limited_bitwise(P):
+def test_euler_vortex_limited_bitwise(P, variant):
     """Table 3's WCCS setup: the same vortex with the rotated characteristic
     limiter of Section 4."""
     N = 50
     q0 = inputs.isentropic_vortex(P, N)
     dom = (-5.0, 5.0, -5.0, 5.0)
-    q, info = gpu_run("euler", P, N, N, q0, True, dom=dom, cfl=CFL[P], t_end=2.0)
+    q, info = gpu_run("euler", P, N, N, q0, True, dom=dom, cfl=CFL[P], t_end=2.0, variant=variant)
     r = oracle_run("euler", P, N, N, q0, True, dom=dom, cfl=CFL[P], t_end=2.0)
     assert_bitwise(q, info, r, f"limited vortex P={P}")
 
 
+@pytest.mark.parametrize("variant", VARIANTS)
 @pytest.mark.parametrize("P", [1, 3])
-def test_euler_modes_limited_bitwise(P):
+def test_euler_modes_limited_bitwise(P, variant):
     """A positive Euler state with gradients of rho e in every direction on a
     ragged mesh, limited, with a uniform patch inside (zero gradient of
     rho e: the rotated direction falls back to (1, 0)) whose edges are
@@ -129,7 +158,7 @@ def test_euler_modes_limited_bitwise(P):
                          for seed, c0, amp in ((11, 2.0, 0.5), (12, 0.0, 0.3), (13, 0.0, 0.3), (14, 6.0, 1.0))])
     q0[:, 0, 5:9, 4:10] = q0[:, 0, 5:6, 4:5]
     q0[:, 1:, 5:9, 4:10] = 0.0
-    q, info = gpu_run("euler", P, Nx, Ny, q0, True, cfl=CFL[P], half_steps=20)
+    q, info = gpu_run("euler", P, Nx, Ny, q0, True, cfl=CFL[P], half_steps=20, variant=variant)
     r = oracle_run("euler", P, Nx, Ny, q0, True, cfl=CFL[P], half_steps=20)
     assert_bitwise(q, info, r, f"limited modes P={P}")
 
