@@ -34,7 +34,7 @@ FP32_VALU_PEAK = 157.3e12  # flop/s (packed / dual-issue)
 CFL_BY_P = [0.4, 0.4, 0.3, 0.25, 0.25]
 
 
-def measured_traffic(kernel: str, N: int):
+def measured_traffic(kernel: str, N: int, sources: str = "1d"):
     """HBM bytes per launch from the committed counter record (FETCH_SIZE and
     WRITE_SIZE, scaled by the copy-kernel calibration), or None when the
     record is for another kernel build or size."""
@@ -46,7 +46,7 @@ def measured_traffic(kernel: str, N: int):
         return None
     from paper_2104_04347_amd.profsum import kernel_source_hash
     e = rec.get(kernel)
-    if not e or e.get("source_sha256") != kernel_source_hash() or e.get("N") != N:
+    if not e or e.get("source_sha256") != kernel_source_hash(sources) or e.get("N") != N:
         return None
     return e["fetch_bytes"] + e["write_bytes"]
 
@@ -172,8 +172,10 @@ def time_2d(args):
     2048 x 2048 periodic mesh of [0, 2]^2 with seeded sine modes; and the
     Euler isentropic vortex of Table 3, P = 3, 1024 x 1024 on [-5, 5]^2,
     unlimited (LCCS) and with the rotated characteristic limiter (WCCS).
-    Binary64.  Algorithmic bytes per launch: every old cell read
-    once and every new cell written once, nc * ndof doubles each."""
+    Binary64, the library's default launch (row marching with prefetch).
+    Algorithmic bytes per launch: every old cell read once and every new cell
+    written once, nc * ndof doubles each; `traffic` is the measured HBM bytes
+    per launch from the committed counter record (null if it is stale)."""
     import torch
     from paper_2104_04347_amd import binding, inputs
     out = {}
@@ -198,9 +200,11 @@ def time_2d(args):
         nc, nd = s.nc, s.nd
         dofs = N * N * nc * nd * args.steps2d
         bpl = 2.0 * N * N * nc * nd * 8
+        kernel = f"k2d_half_step_rows<{eq},P={P},{'limiter' if lim else 'no limiter'},prefetch>"
         e = {"value": dofs / wall, "unit": "cell-DOF updates/s", "N": N, "P": P, "limiter": lim,
-             "cfl": cfl, "half_steps": args.steps2d, "launch_us": launch_s * 1e6, "bytes_per_launch": bpl,
-             "hbm_frac": bpl / launch_s / HBM_PEAK, "valid": bool((info.flags & 3) == 0)}
+             "cfl": cfl, "half_steps": args.steps2d, "kernel": kernel, "launch_us": launch_s * 1e6,
+             "bytes_per_launch": bpl, "hbm_frac": bpl / launch_s / HBM_PEAK,
+             "traffic": measured_traffic(kernel, N, "2d"), "valid": bool((info.flags & 3) == 0)}
         s.close()
         if not args.no_cpu:
             import oracle

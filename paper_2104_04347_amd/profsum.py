@@ -10,13 +10,14 @@ Measurement tooling; runs on any host, no GPU needed.
       per-kernel mean / min / max of every counter of a --pmc run
 
   python -m paper_2104_04347_amd.profsum traffic FETCH_DB WRITE_DB --kernel SUBSTR
-          --key NAME --N N --copy-mib M [--out profiles/traffic.json]
+          --key NAME --N N --copy-mib M [--sources 1d|2d] [--out profiles/traffic.json]
       HBM bytes per dispatch of the kernel whose name contains SUBSTR, from a
       FETCH_SIZE run and a WRITE_SIZE run (both in KiB per dispatch), each
       scaled by what the same counter reads for the runtime's device-to-device
       copy of M MiB profiled in the same run (the largest copy dispatch).  The
       record is keyed by NAME and stamped with the SHA-256 of the kernel
-      sources, so that a later kernel change invalidates it.
+      sources (the 1D or the 2D half-step's), so that a later kernel change
+      invalidates it.
 """
 from __future__ import annotations
 
@@ -33,14 +34,16 @@ CSRC = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
 COPY_KERNEL = "__amd_rocclr_copyBuffer"
 
 
-# the sources the single-instance 1D half-step kernel is compiled from
+# the sources the single-instance 1D half-step kernel is compiled from, and
+# those of the 2D half-step kernels
 KERNEL_SOURCES = ("wcc_cell.hpp", "wcc_internal.hpp", "wcc_kernels.hip", "wcc_tile.hpp")
+KERNEL_SOURCES_2D = ("wcc2d_cell.hpp", "wcc2d_internal.hpp", "wcc2d_kernels.hip", "wcc_internal.hpp", "wcc_tile.hpp")
 
 
-def kernel_source_hash() -> str:
-    """SHA-256 over the sources of the 1D half-step kernel."""
+def kernel_source_hash(sources: str = "1d") -> str:
+    """SHA-256 over the sources of the 1D (or 2D) half-step kernel."""
     h = hashlib.sha256()
-    for name in KERNEL_SOURCES:
+    for name in (KERNEL_SOURCES if sources == "1d" else KERNEL_SOURCES_2D):
         with open(os.path.join(CSRC, name), "rb") as f:
             h.update(name.encode() + b"\0" + f.read())
     return h.hexdigest()
@@ -92,14 +95,16 @@ def _one(db: str, counter: str, match: str):
     return ks[0], vals, max(copies)
 
 
-def traffic(fetch_db: str, write_db: str, match: str, key: str, N: int, copy_mib: int, out: str | None) -> dict:
+def traffic(fetch_db: str, write_db: str, match: str, key: str, N: int, copy_mib: int, out: str | None,
+            sources: str = "1d") -> dict:
     name, fv, fcopy = _one(fetch_db, "FETCH_SIZE", match)
     _, wv, wcopy = _one(write_db, "WRITE_SIZE", match)
     copy_kib = copy_mib * 1024.0
     ff, wf = copy_kib / fcopy, copy_kib / wcopy
     rec = {
         "kernel_name": name,
-        "source_sha256": kernel_source_hash(),
+        "source_sha256": kernel_source_hash(sources),
+        "sources": sources,
         "N": N,
         "dispatches": [len(fv), len(wv)],
         "fetch_kib_raw_mean": statistics.fmean(fv),
@@ -139,6 +144,7 @@ def main(argv=None) -> None:
     r.add_argument("--key", required=True)
     r.add_argument("--N", type=int, required=True)
     r.add_argument("--copy-mib", type=int, required=True)
+    r.add_argument("--sources", choices=("1d", "2d"), default="1d")
     r.add_argument("--out")
     a = ap.parse_args(argv)
     if a.cmd == "trace":
@@ -146,7 +152,8 @@ def main(argv=None) -> None:
     elif a.cmd == "counters":
         print(counters_table(a.db))
     else:
-        json.dump(traffic(a.fetch_db, a.write_db, a.kernel, a.key, a.N, a.copy_mib, a.out), sys.stdout, indent=1)
+        json.dump(traffic(a.fetch_db, a.write_db, a.kernel, a.key, a.N, a.copy_mib, a.out, a.sources), sys.stdout,
+                  indent=1)
         print()
 
 
