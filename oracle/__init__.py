@@ -135,6 +135,7 @@ class Problem:
         s.N = self.N
         s.bc = BCS[self.bc]
         s.limiter = 1 if self.limiter else 0
+        s.bc = BCS2D[self.bc]
         s.x_left = self.x_left
         s.x_right = self.x_right
         s.a = self.a
@@ -297,7 +298,7 @@ class _Problem2D(ctypes.Structure):
         ("Nx", ctypes.c_int64),
         ("Ny", ctypes.c_int64),
         ("limiter", ctypes.c_int32),
-        ("pad", ctypes.c_int32),
+        ("bc", ctypes.c_int32),
         ("x_left", ctypes.c_double),
         ("x_right", ctypes.c_double),
         ("y_left", ctypes.c_double),
@@ -322,7 +323,7 @@ def _load2d():
     lib.wcc2d_oracle_js_indicator.restype = ctypes.c_double
     lib.wcc2d_oracle_ndof.argtypes = [ctypes.c_int32]
     lib.wcc2d_oracle_ndof.restype = ctypes.c_int64
-    lib.wcc2d_oracle_max_speed.argtypes = [P(_Problem2D), dp, P(ctypes.c_int32)]
+    lib.wcc2d_oracle_max_speed.argtypes = [P(_Problem2D), ctypes.c_int32, dp, P(ctypes.c_int32)]
     lib.wcc2d_oracle_max_speed.restype = ctypes.c_double
     lib.wcc2d_oracle_half_step.argtypes = [P(_Problem2D), ctypes.c_int32, dp, ctypes.c_double, dp, dp,
                                            P(ctypes.c_int32)]
@@ -343,12 +344,18 @@ def dof2d(k: int, l: int) -> int:
     return n * (n + 1) // 2 + l
 
 
+BCS2D = {"periodic": 0, "transmissive": 1}
+
+
 @dataclass
 class Problem2D:
-    """u_t + f(u)_x + g(u)_y = 0 on a periodic rectangle (Eq. 2DHCL);
-    advection f = a u, g = b u; Burgers f = g = u^2/2; Euler (rho, rho u,
-    rho v, rho e), limited in the characteristic fields of the rotated
-    decomposition (Section 4)."""
+    """u_t + f(u)_x + g(u)_y = 0 on a rectangle (Eq. 2DHCL); advection
+    f = a u, g = b u; Burgers f = g = u^2/2; Euler (rho, rho u, rho v, rho e),
+    limited in the characteristic fields of the rotated decomposition
+    (Section 4).  Periodic: Nx x Ny cells on both meshes.  Transmissive: the
+    mesh of parity 0 has the (Nx+1) x (Ny+1) cells centred at the mesh points
+    (edges included), parity 1 the Nx x Ny cells between them (Section 3.1);
+    ghosts copy the adjacent cell."""
     equation: str
     P: int
     Nx: int
@@ -362,6 +369,7 @@ class Problem2D:
     b: float = 1.0
     gamma: float = 1.4
     eps: float = 1e-40
+    bc: str = "periodic"
 
     @property
     def nc(self) -> int:
@@ -370,6 +378,15 @@ class Problem2D:
     @property
     def nd(self) -> int:
         return ndof2d(self.P)
+
+    def mesh(self, parity: int) -> tuple:
+        """(cells in x, cells in y) of the mesh of this parity."""
+        e = 1 if (self.bc == "transmissive" and parity % 2 == 0) else 0
+        return self.Nx + e, self.Ny + e
+
+    def mesh_shape(self, parity: int) -> tuple:
+        nx, ny = self.mesh(parity)
+        return (self.nc, self.nd, ny, nx)
 
     @property
     def dx(self) -> float:
@@ -381,13 +398,15 @@ class Problem2D:
 
     @property
     def shape(self):
-        return (self.nc, self.nd, self.Ny, self.Nx)
+        """State shape on the parity-0 mesh."""
+        return self.mesh_shape(0)
 
     def c_struct(self) -> _Problem2D:
         s = _Problem2D()
         s.equation = EQUATIONS[self.equation]
         s.P, s.Nx, s.Ny = self.P, self.Nx, self.Ny
         s.limiter = 1 if self.limiter else 0
+        s.bc = BCS2D[self.bc]
         s.x_left, s.x_right, s.y_left, s.y_right = self.x_left, self.x_right, self.y_left, self.y_right
         s.a, s.b, s.gamma, s.eps = self.a, self.b, self.gamma, self.eps
         return s
@@ -420,14 +439,14 @@ def js_indicator2d(P: int, d: np.ndarray) -> float:
     return _load2d().wcc2d_oracle_js_indicator(int(P), _dp(d))
 
 
-def max_speed2d(pb: Problem2D, q: np.ndarray) -> tuple:
+def max_speed2d(pb: Problem2D, q: np.ndarray, parity: int = 0) -> tuple:
     """(largest s_x/dx + s_y/dy over the stored averages, status bits)."""
     lib = _load2d()
     q = np.ascontiguousarray(q, dtype=np.float64)
-    assert q.shape == pb.shape
+    assert q.shape == pb.mesh_shape(parity)
     fl = ctypes.c_int32(0)
     cs = pb.c_struct()
-    v = lib.wcc2d_oracle_max_speed(ctypes.byref(cs), _dp(q), ctypes.byref(fl))
+    v = lib.wcc2d_oracle_max_speed(ctypes.byref(cs), int(parity), _dp(q), ctypes.byref(fl))
     return v, fl.value
 
 
@@ -435,8 +454,8 @@ def half_step2d(pb: Problem2D, parity: int, q: np.ndarray, dt: float):
     """One half-step from mesh `parity`: (new state, smax of the new averages, flags)."""
     lib = _load2d()
     q = np.ascontiguousarray(q, dtype=np.float64)
-    assert q.shape == pb.shape
-    out = np.empty_like(q)
+    assert q.shape == pb.mesh_shape(parity)
+    out = np.empty(pb.mesh_shape(1 - parity))
     sm = ctypes.c_double(0.0)
     fl = ctypes.c_int32(0)
     cs = pb.c_struct()
@@ -452,9 +471,12 @@ def run2d(pb: Problem2D, q: np.ndarray, parity: int = 0, t: float = 0.0, t_end: 
     """March 2D half-steps: dt = cfl / smax (smax the largest s_x/dx + s_y/dy),
     clipped to t_end, or dt_fixed."""
     lib = _load2d()
-    buf = np.ascontiguousarray(q, dtype=np.float64).copy()
-    assert buf.shape == pb.shape
-    smax, _ = max_speed2d(pb, buf)
+    q = np.ascontiguousarray(q, dtype=np.float64)
+    assert q.shape == pb.mesh_shape(parity)
+    # room for the larger mesh: the state changes mesh every half-step
+    buf = np.zeros(pb.nc * pb.nd * (pb.Nx + 1) * (pb.Ny + 1))
+    buf[: q.size] = q.ravel()
+    smax, _ = max_speed2d(pb, q, parity)
     cp = ctypes.c_int32(parity)
     ct = ctypes.c_double(t)
     cs_ = ctypes.c_double(smax)
@@ -464,4 +486,6 @@ def run2d(pb: Problem2D, q: np.ndarray, parity: int = 0, t: float = 0.0, t_end: 
                                  float(t_end), float(cfl), float(dt_fixed), int(max_half_steps), ctypes.byref(fl))
     if taken < 0:
         raise ValueError("oracle rejected the 2D problem")
-    return RunResult(buf, cp.value, ct.value, cs_.value, int(taken), fl.value)
+    shp = pb.mesh_shape(cp.value)
+    out = buf[: int(np.prod(shp))].reshape(shp).copy()
+    return RunResult(out, cp.value, ct.value, cs_.value, int(taken), fl.value)

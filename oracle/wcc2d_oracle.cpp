@@ -39,7 +39,7 @@
 //
 // Readings (design notes of the repository): state = point value; time step
 // dt = cfl / max_cells(s_x/dx + s_y/dy) from the cell averages, recomputed
-// every half-step and clipped to t_end; periodic boundaries only.
+// every half-step and clipped to t_end; periodic or transmissive boundaries.
 
 #include <cmath>
 #include <cstdint>
@@ -98,9 +98,9 @@ extern "C" {
 typedef struct {
   int32_t equation;  // 0 advection (f = a u, g = b u), 1 Burgers (f = g = u^2/2), 2 Euler
   int32_t P;         // degree 0..4
-  int64_t Nx, Ny;    // cells per direction (periodic)
-  int32_t limiter;   // scalar equations only
-  int32_t pad;
+  int64_t Nx, Ny;    // mesh intervals per direction
+  int32_t limiter;
+  int32_t bc;        // 0 periodic, 1 transmissive (see Mesh below)
   double x_left, x_right, y_left, y_right;
   double a, b;       // advection velocity
   double gamma;
@@ -427,11 +427,32 @@ void char_limit2d(int P, double gamma, double eps, double dx, double dy, const d
       for (int l = 0; l <= n; ++l) D[r][n - l][l] = out[r][n - l][l];
 }
 
+// The two meshes of Section 3.1.  Periodic: Nx x Ny cells on both, centred
+// at (x_left + i dx, y_left + j dy) (parity 0) and shifted by (dx/2, dy/2)
+// (parity 1), indices wrapped.  Transmissive: parity 0 is the mesh of the
+// (Nx+1) x (Ny+1) mesh points x_i, y_j (the domain's edges included),
+// parity 1 the Nx x Ny cells between them; a new parity-0 cell on the edge
+// has parents outside the staggered mesh, which are copies (all DOFs) of the
+// adjacent staggered cell -- the 1D transmissive ghost rule applied in each
+// direction, corners included.
 struct Mesh {
-  int64_t Nx, Ny;
-  int64_t wrapx(int64_t i) const { return (i % Nx + Nx) % Nx; }
-  int64_t wrapy(int64_t j) const { return (j % Ny + Ny) % Ny; }
+  int64_t nx, ny;     // cells of this mesh
+  bool periodic;
+  int64_t mapx(int64_t i) const {
+    if (periodic) return (i % nx + nx) % nx;
+    return i < 0 ? 0 : (i >= nx ? nx - 1 : i);
+  }
+  int64_t mapy(int64_t j) const {
+    if (periodic) return (j % ny + ny) % ny;
+    return j < 0 ? 0 : (j >= ny ? ny - 1 : j);
+  }
 };
+
+inline Mesh mesh_of(const wcc2d_oracle_problem& pb, int parity) {
+  const bool per = pb.bc == 0;
+  const int64_t e = (per || parity == 1) ? 0 : 1;
+  return Mesh{pb.Nx + e, pb.Ny + e, per};
+}
 
 // Wave-speed rate s_x/dx + s_y/dy of a conserved average (1/time units).
 double speed_rate(const wcc2d_oracle_problem& pb, const double* ab, double idx, double idy, int& flag) {
@@ -461,11 +482,14 @@ void stored_average(int P, int nc, const double q[NCMAX][32], double* ab) {
   }
 }
 
-void load(const wcc2d_oracle_problem& pb, const double* qs, int64_t i, int64_t j, double q[NCMAX][32]) {
+// State of cell (i, j) of mesh M: planes [c][dof] of M.nx * M.ny values,
+// row-major (x fastest).
+void load(const wcc2d_oracle_problem& pb, const Mesh& M, const double* qs, int64_t i, int64_t j,
+          double q[NCMAX][32]) {
   const int nd = ndof(pb.P), nc = ncomp(pb);
-  const int64_t plane = pb.Nx * pb.Ny;
+  const int64_t plane = M.nx * M.ny;
   for (int c = 0; c < nc; ++c)
-    for (int d = 0; d < nd; ++d) q[c][d] = qs[((int64_t)(c * nd + d)) * plane + j * pb.Nx + i];
+    for (int d = 0; d < nd; ++d) q[c][d] = qs[((int64_t)(c * nd + d)) * plane + j * M.nx + i];
 }
 
 // One half-step from mesh `parity` with time step dt.  Returns the largest
@@ -483,25 +507,26 @@ void half_step(const wcc2d_oracle_problem& pb, int parity, const double* qin, do
       cx[k][m] = -lamx * K.CKR[k][m];
       cy[k][m] = -lamy * K.CKR[k][m];
     }
-  const Mesh M{pb.Nx, pb.Ny};
-  std::vector<Old> old((size_t)(pb.Nx * pb.Ny));
+  const Mesh M = mesh_of(pb, parity), MN = mesh_of(pb, 1 - parity);
+  std::vector<Old> old((size_t)(M.nx * M.ny));
   double q[NCMAX][32];
-  for (int64_t j = 0; j < pb.Ny; ++j)
-    for (int64_t i = 0; i < pb.Nx; ++i) {
-      load(pb, qin, i, j, q);
-      old_cell(pb, q, cx, cy, old[(size_t)(j * pb.Nx + i)]);
+  for (int64_t j = 0; j < M.ny; ++j)
+    for (int64_t i = 0; i < M.nx; ++i) {
+      load(pb, M, qin, i, j, q);
+      old_cell(pb, q, cx, cy, old[(size_t)(j * M.nx + i)]);
     }
+  // parents of new cell (i, j): old cells (i+off .. i+off+1, j+off .. j+off+1)
   const int64_t off = parity == 0 ? 0 : -1;
-  const int64_t plane = pb.Nx * pb.Ny;
+  const int64_t plane = MN.nx * MN.ny;
   double sm = 0.0;
   int fl = 0;
-  for (int64_t j = 0; j < pb.Ny; ++j)
-    for (int64_t i = 0; i < pb.Nx; ++i) {
-      const int64_t i0 = M.wrapx(i + off), i1 = M.wrapx(i + off + 1), j0 = M.wrapy(j + off), j1 = M.wrapy(j + off + 1);
-      const Old& A = old[(size_t)(j0 * pb.Nx + i0)];   // lower-left vertex of the new cell
-      const Old& B = old[(size_t)(j1 * pb.Nx + i0)];   // upper-left
-      const Old& C = old[(size_t)(j0 * pb.Nx + i1)];   // lower-right
-      const Old& Dd = old[(size_t)(j1 * pb.Nx + i1)];  // upper-right
+  for (int64_t j = 0; j < MN.ny; ++j)
+    for (int64_t i = 0; i < MN.nx; ++i) {
+      const int64_t i0 = M.mapx(i + off), i1 = M.mapx(i + off + 1), j0 = M.mapy(j + off), j1 = M.mapy(j + off + 1);
+      const Old& A = old[(size_t)(j0 * M.nx + i0)];   // lower-left vertex of the new cell
+      const Old& B = old[(size_t)(j1 * M.nx + i0)];   // upper-left
+      const Old& C = old[(size_t)(j0 * M.nx + i1)];   // lower-right
+      const Old& Dd = old[(size_t)(j1 * M.nx + i1)];  // upper-right
       double ab[NCMAX];
       double D[NCMAX][PMAX + 1][PMAX + 1] = {};
       for (int c = 0; c < nc; ++c) {
@@ -555,7 +580,7 @@ void half_step(const wcc2d_oracle_problem& pb, int parity, const double* qin, do
             const int k = n - l;
             if (k % 2 == 0 && l % 2 == 0) pv = std::fma(K.NQA[k][l], D[c][k][l], pv);
           }
-        const int64_t cell = j * pb.Nx + i;
+        const int64_t cell = j * MN.nx + i;
         qout[((int64_t)(c * nd)) * plane + cell] = pv;
         bool ok = std::isfinite(pv);
         for (int n = 1; n <= P; ++n)
@@ -589,17 +614,19 @@ double wcc2d_oracle_js_indicator(int32_t P, const double* d) {
   return w2d::js2d(P, D);
 }
 
-// Largest wave-speed rate s_x/dx + s_y/dy over the averages of a stored state.
-double wcc2d_oracle_max_speed(const wcc2d_oracle_problem* pb, const double* q, int32_t* flags) {
+// Largest wave-speed rate s_x/dx + s_y/dy over the averages of a stored
+// state on mesh `parity`.
+double wcc2d_oracle_max_speed(const wcc2d_oracle_problem* pb, int32_t parity, const double* q, int32_t* flags) {
   const int nc = w2d::ncomp(*pb);
   const double dx = (pb->x_right - pb->x_left) / (double)pb->Nx, dy = (pb->y_right - pb->y_left) / (double)pb->Ny;
   const double idx = 1.0 / dx, idy = 1.0 / dy;
+  const w2d::Mesh M = w2d::mesh_of(*pb, parity);
   double sm = 0.0;
   int fl = 0;
   double qc[w2d::NCMAX][32], ab[w2d::NCMAX];
-  for (int64_t j = 0; j < pb->Ny; ++j)
-    for (int64_t i = 0; i < pb->Nx; ++i) {
-      w2d::load(*pb, q, i, j, qc);
+  for (int64_t j = 0; j < M.ny; ++j)
+    for (int64_t i = 0; i < M.nx; ++i) {
+      w2d::load(*pb, M, q, i, j, qc);
       w2d::stored_average(pb->P, nc, qc, ab);
       sm = std::fmax(sm, w2d::speed_rate(*pb, ab, idx, idy, fl));
     }
@@ -639,7 +666,7 @@ int32_t wcc2d_oracle_old_cell(const wcc2d_oracle_problem* pb, const double* q, d
 
 int32_t wcc2d_oracle_half_step(const wcc2d_oracle_problem* pb, int32_t parity, const double* qin, double dt,
                                double* qout, double* smax, int32_t* flags) {
-  if (!pb || pb->P < 0 || pb->P > w2d::PMAX || pb->Nx < 2 || pb->Ny < 2) return -1;
+  if (!pb || pb->P < 0 || pb->P > w2d::PMAX || pb->Nx < 2 || pb->Ny < 2 || pb->bc < 0 || pb->bc > 1) return -1;
   int fl = 0;
   w2d::half_step(*pb, parity, qin, dt, qout, smax, &fl);
   if (flags) *flags = fl;
@@ -648,13 +675,14 @@ int32_t wcc2d_oracle_half_step(const wcc2d_oracle_problem* pb, int32_t parity, c
 
 // March half-steps: dt = cfl / smax (smax: wave-speed rate of the current
 // state), clipped to t_end; or dt_fixed when > 0.  q (in/out) holds the state
-// of mesh *parity.  Stops at t_end, after max_half_steps, or when a status
-// bit is raised.  Returns the number of half-steps taken, -1 on bad input.
+// of mesh *parity and has room for the larger mesh.  Stops at t_end, after
+// max_half_steps, or when a status bit is raised.  Returns the number of
+// half-steps taken, -1 on bad input.
 int64_t wcc2d_oracle_run(const wcc2d_oracle_problem* pb, int32_t* parity, double* t, double* smax, double* q,
                          double t_end, double cfl, double dt_fixed, int64_t max_half_steps, int32_t* flags) {
-  if (!pb || pb->P < 0 || pb->P > w2d::PMAX || pb->Nx < 2 || pb->Ny < 2) return -1;
-  const size_t n = (size_t)(w2d::ncomp(*pb) * w2d::ndof(pb->P)) * (size_t)(pb->Nx * pb->Ny);
-  std::vector<double> tmp(n);
+  if (!pb || pb->P < 0 || pb->P > w2d::PMAX || pb->Nx < 2 || pb->Ny < 2 || pb->bc < 0 || pb->bc > 1) return -1;
+  const size_t per_cell = (size_t)(w2d::ncomp(*pb) * w2d::ndof(pb->P));
+  std::vector<double> tmp(per_cell * (size_t)((pb->Nx + 1) * (pb->Ny + 1)));
   int64_t taken = 0;
   *flags = 0;
   while (taken < max_half_steps && *t < t_end) {
@@ -675,7 +703,8 @@ int64_t wcc2d_oracle_run(const wcc2d_oracle_problem* pb, int32_t* parity, double
     int fl = 0;
     double sm = 0.0;
     w2d::half_step(*pb, *parity, q, dt, tmp.data(), &sm, &fl);
-    std::memcpy(q, tmp.data(), n * sizeof(double));
+    const w2d::Mesh MN = w2d::mesh_of(*pb, 1 - *parity);
+    std::memcpy(q, tmp.data(), per_cell * (size_t)(MN.nx * MN.ny) * sizeof(double));
     *parity ^= 1;
     *t = tn;
     *smax = sm;

@@ -373,11 +373,14 @@ def dof_pairs(P: int):
     return [(n - l, l) for n in range(P + 1) for l in range(n + 1)]
 
 
-def centers2d(x_left, x_right, y_left, y_right, Nx, Ny, parity):
-    """Cell centres (X, Y), arrays of shape (Ny, Nx); periodic meshes of Nx x Ny
-    cells, the staggered mesh shifted by (dx/2, dy/2)."""
-    x = centers(x_left, x_right, Nx, Nx, parity)
-    y = centers(y_left, y_right, Ny, Ny, parity)
+def centers2d(x_left, x_right, y_left, y_right, Nx, Ny, parity, bc: str = "periodic"):
+    """Cell centres (X, Y) of the mesh of this parity (Section 3.1): periodic,
+    Nx x Ny cells on both meshes, the staggered one shifted by (dx/2, dy/2);
+    transmissive, the (Nx+1) x (Ny+1) mesh points on parity 0 (edges
+    included) and the Nx x Ny cells between them on parity 1.  Arrays of
+    shape (rows, columns)."""
+    x = centers(x_left, x_right, Nx, n_cells(Nx, bc, parity), parity)
+    y = centers(y_left, y_right, Ny, n_cells(Ny, bc, parity), parity)
     return np.meshgrid(x, y)
 
 
@@ -473,3 +476,35 @@ def isentropic_vortex(P: int, N: int, parity: int = 0, gamma: float = 1.4, psi: 
         for c in range(4):
             q[c, dof2d(k, l)] = h ** (k + l) * np.broadcast_to(fns[(k, l)][c](X, Y), X.shape)
     return q
+
+
+# The two 2D Riemann problems of Section 5.3 (density, x- and y-velocity,
+# pressure in the quadrants [-1,0]x[-1,0], [-1,0]x[0,1], [0,1]x[0,1],
+# [0,1]x[-1,0]).
+RIEMANN2D = {
+    1: ((0.138, 1.206, 1.206, 0.029), (0.5323, 1.206, 0.0, 0.3), (1.5, 0.0, 0.0, 1.5), (0.5323, 0.0, 1.206, 0.3)),
+    2: ((1.0, -0.75, 0.5, 1.0), (2.0, 0.75, 0.5, 1.0), (1.0, 0.75, -0.5, 1.0), (3.0, -0.75, -0.5, 1.0)),
+}
+
+
+def riemann2d(config: int, P: int, N: int, parity: int = 0, gamma: float = 1.4):
+    """2D Riemann problem `config` on [-1, 1]^2 with N x N intervals,
+    transmissive: every cell holds the exact mean of the conserved variables
+    over the cell (area-weighted over the quadrants it overlaps) as its point
+    value, derivatives zero (the piecewise-constant data have none)."""
+    states = RIEMANN2D[config]
+    h = 2.0 / N
+    X, Y = centers2d(-1.0, 1.0, -1.0, 1.0, N, N, parity, "transmissive")
+
+    def frac_neg(c):           # fraction of [c - h/2, c + h/2] below 0
+        return np.clip((0.0 - (c - 0.5 * h)) / h, 0.0, 1.0)
+
+    fx, fy = frac_neg(X), frac_neg(Y)
+    weights = (fx * fy, fx * (1 - fy), (1 - fx) * (1 - fy), (1 - fx) * fy)
+    q = np.zeros((4, ndof2d(P)) + X.shape)
+    for w, (rho, u, v, p) in zip(weights, states):
+        cons = (rho, rho * u, rho * v, p / (gamma - 1.0) + 0.5 * rho * (u * u + v * v))
+        for c in range(4):
+            q[c, 0] += w * cons[c]
+    return q
+

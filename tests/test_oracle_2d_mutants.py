@@ -1,6 +1,7 @@
-"""The 2D pins must catch plausible mistakes in the 2D oracle: each case
-plants one mistake in a copy of wcc2d_oracle.cpp, builds it with the real 1D
-source, and checks that a quick selection of the 2D pins fails on it."""
+"""The 2D pins must catch plausible mistakes in the 2D oracle (on the periodic
+and on the transmissive meshes): each case plants one mistake in a copy of
+wcc2d_oracle.cpp, builds it with the real 1D source, and checks that a quick
+selection of the 2D pins fails on it."""
 import subprocess
 
 import pytest
@@ -9,6 +10,7 @@ import oracle
 from oracle import build as obuild
 
 import test_oracle_2d as t2
+import test_oracle_2d_transmissive as t2t
 
 MUTANTS = {
     "LD quarter-average sign": ("ld = std::fma(((k + l) % 2) ? -qa : qa, x, ld);",
@@ -39,6 +41,9 @@ MUTANTS = {
     "left eigenvector sign": ("{-ut, -ny, nx, 0.0}", "{ut, -ny, nx, 0.0}"),
     "right eigenvector energy entry": ("{1.0, u, vv, 0.5 * q2}", "{1.0, u, vv, q2}"),
     "tangential velocity sign": ("ut = std::fma(vv, nx, -(u * ny))", "ut = std::fma(vv, nx, u * ny)"),
+    "transmissive ghost wraps in x": ("    return i < 0 ? 0 : (i >= nx ? nx - 1 : i);", "    return (i % nx + nx) % nx;"),
+    "transmissive edge mesh missing": ("const int64_t e = (per || parity == 1) ? 0 : 1;",
+                                       "const int64_t e = (per || parity == 0) ? 0 : 1;"),
 }
 
 
@@ -59,6 +64,8 @@ def quick_pins() -> list:
         ("square", lambda: [t2.test_limiter_tames_square_wave(P) for P in (2, 3)]),
         ("Appendix B", lambda: [t2.test_appendix_b_integrals_exact(P) for P in (2, 3)]),
         ("Burgers diagonal", lambda: t2.test_burgers_diagonal_order(2)),
+        ("transmissive 1D Euler", lambda: t2t.test_reduces_to_1d_euler_transmissive(2)),
+        ("transmissive interior", lambda: t2t.test_interior_equals_periodic("burgers", 3)),
     ]
     failed = []
     for name, fn in checks:

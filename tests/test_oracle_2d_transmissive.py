@@ -1,0 +1,149 @@
+"""Pins of the 2D oracle on the non-periodic meshes of Section 3.1: parity 0
+holds the (Nx+1) x (Ny+1) cells centred at the mesh points (the domain's
+edges included), parity 1 the Nx x Ny cells between them, and the parents
+that a new edge cell lacks are copies of the adjacent staggered cell
+(transmissive ghosts).  Each pin is fixed by something other than the 2D
+oracle's own index arithmetic:
+
+* data independent of y follows the 1D oracle with its transmissive ghosts
+  (pinned there by Sod's problem and the invariants) row by row;
+* away from the edges, inside the domain of dependence, the transmissive
+  run equals the periodic run bit for bit (same cells, same dt);
+* a uniform state stays uniform bit for bit on both meshes;
+* x-y symmetric data stay symmetric;
+* the first 2D Riemann problem of Section 5.3 keeps rho > 0, p > 0 and its
+  diagonal symmetry.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2104_04347_amd import inputs
+
+DOF = inputs.dof2d
+CFL = {1: 0.4, 2: 0.3, 3: 0.25}
+
+
+def test_mesh_shapes():
+    pb = oracle.Problem2D("burgers", 2, 7, 5, bc="transmissive")
+    assert pb.mesh_shape(0) == (1, 6, 6, 8) and pb.mesh_shape(1) == (1, 6, 5, 7)
+    X, Y = inputs.centers2d(0.0, 7.0, 0.0, 5.0, 7, 5, 0, "transmissive")
+    assert X.shape == (6, 8) and X[0, 0] == 0.0 and X[0, -1] == 7.0 and Y[-1, 0] == 5.0
+    X, Y = inputs.centers2d(0.0, 7.0, 0.0, 5.0, 7, 5, 1, "transmissive")
+    assert X.shape == (5, 7) and X[0, 0] == 0.5 and Y[-1, 0] == 4.5
+
+
+@pytest.mark.parametrize("eq", ["advection", "burgers", "euler"])
+@pytest.mark.parametrize("P", [1, 3])
+def test_uniform_state_kept(eq, P):
+    Nx, Ny = 9, 6
+    pb = oracle.Problem2D(eq, P, Nx, Ny, limiter=True, bc="transmissive", x_right=1.5, y_right=1.0, a=0.6, b=-0.3)
+    q = np.zeros(pb.mesh_shape(0))
+    vals = (1.1, 0.3, -0.2, 2.5) if eq == "euler" else (0.7,)
+    for c, v in enumerate(vals):
+        q[c, 0] = v
+    r = oracle.run2d(pb, q, cfl=CFL[P], max_half_steps=5)
+    assert r.flags == 0 and r.parity == 1 and r.q.shape == pb.mesh_shape(1)
+    for c, v in enumerate(vals):
+        assert np.all(r.q[c, 0] == v)
+        assert np.all(r.q[c, 1:] == 0.0)
+
+
+@pytest.mark.parametrize("P", [1, 2, 3])
+def test_reduces_to_1d_euler_transmissive(P):
+    """Euler data depending on x only (a jump and a density sine, v = 0):
+    every row of the 2D run follows the 1D transmissive oracle, limiter off,
+    across several returns to the mesh with edge cells."""
+    N, M = 30, 3
+    data = inputs.EulerPiecewise(np.array([0.9]), np.array([1.0, 0.6]), np.array([0.2, -0.1]),
+                                 np.array([1.0, 0.7]), sine_amp=0.2, sine_w=2.0)
+    x = inputs.centers(0.0, 2.0, N, N + 1, 0)
+    q1 = inputs.euler_taylor(data, x, 2.0 / N, P)
+    pb1 = oracle.Problem("euler", P, N, bc="transmissive", limiter=False, x_left=0.0, x_right=2.0)
+    dt = 0.1 * pb1.dx
+    r1 = oracle.run(pb1, q1, dt_fixed=dt, max_half_steps=8)
+    pb2 = oracle.Problem2D("euler", P, N, M, bc="transmissive", x_right=2.0, y_right=2.0 * M / N)
+    q2 = np.zeros(pb2.mesh_shape(0))
+    for k in range(P + 1):
+        q2[0, DOF(k, 0)] = q1[0, k]
+        q2[1, DOF(k, 0)] = q1[1, k]
+        q2[3, DOF(k, 0)] = q1[2, k]
+    r2 = oracle.run2d(pb2, q2, dt_fixed=dt, max_half_steps=8)
+    assert r1.parity == r2.parity == 0 and r2.q.shape == pb2.mesh_shape(0)
+    for c1, c2 in ((0, 0), (1, 1), (2, 3)):
+        for k in range(P + 1):
+            got = r2.q[c2, DOF(k, 0)]
+            np.testing.assert_allclose(got, np.broadcast_to(r1.q[c1, k], got.shape), rtol=0,
+                                       atol=2e-13 * max(1.0, np.abs(r1.q[c1, k]).max()))
+    assert np.all(r2.q[2] == 0.0)
+
+
+@pytest.mark.parametrize("eq", ["advection", "burgers"])
+@pytest.mark.parametrize("P", [1, 3])
+def test_interior_equals_periodic(eq, P):
+    """With a fixed dt, a cell whose domain of dependence stays clear of the
+    edges sees the same parents as on the periodic mesh (the cell centres of
+    both meshes coincide): bit-identical after 6 half-steps."""
+    Nx, Ny, n = 26, 22, 6
+    fn = inputs.modes2d(7)
+    dom = (0.0, 2.0, 0.0, 2.0)
+    per = oracle.Problem2D(eq, P, Nx, Ny, limiter=True, x_right=2.0, y_right=2.0, a=0.7, b=-0.4)
+    tra = oracle.Problem2D(eq, P, Nx, Ny, limiter=True, bc="transmissive", x_right=2.0, y_right=2.0, a=0.7, b=-0.4)
+    qp = inputs.taylor2d(fn, P, Nx, Ny, dom)
+    qt = np.zeros(tra.mesh_shape(0))
+    X, Y = inputs.centers2d(*dom, Nx, Ny, 0, "transmissive")
+    hx, hy = 2.0 / Nx, 2.0 / Ny
+    for k, l in inputs.dof_pairs(P):
+        qt[0, DOF(k, l)] = hx ** k * hy ** l * fn.deriv(X, Y, k, l)
+    assert np.array_equal(qt[:, :, :Ny, :Nx], qp)
+    dt = 0.02
+    rp = oracle.run2d(per, qp, dt_fixed=dt, max_half_steps=n)
+    rt = oracle.run2d(tra, qt, dt_fixed=dt, max_half_steps=n)
+    assert rp.parity == rt.parity == 0
+    inner = (slice(None), slice(None), slice(n, Ny - n), slice(n, Nx - n))
+    assert np.array_equal(rt.q[inner], rp.q[inner])
+    # and the edges do differ (the ghosts are not periodic images)
+    assert not np.array_equal(rt.q[:, :, :Ny, :Nx], rp.q)
+
+
+def _transpose_state(P, q):
+    out = np.empty_like(q.transpose(0, 1, 3, 2))
+    for k, l in inputs.dof_pairs(P):
+        out[:, DOF(l, k)] = q[:, DOF(k, l)].transpose(0, 2, 1)
+    return out
+
+
+@pytest.mark.parametrize("P", [2, 3])
+def test_xy_symmetry_transmissive(P):
+    N = 20
+    fn = inputs.Modes2D(0.3, np.array([0.4, 0.25]), np.pi * np.array([1.0, 2.0]), np.pi * np.array([2.0, 1.0]),
+                        np.array([0.3, 0.3]))
+    pb = oracle.Problem2D("burgers", P, N, N, limiter=True, bc="transmissive", x_right=2.0, y_right=2.0)
+    X, Y = inputs.centers2d(0.0, 2.0, 0.0, 2.0, N, N, 0, "transmissive")
+    q = np.zeros(pb.mesh_shape(0))
+    for k, l in inputs.dof_pairs(P):
+        q[0, DOF(k, l)] = (2.0 / N) ** (k + l) * fn.deriv(X, Y, k, l)
+    q = 0.5 * (q + _transpose_state(P, q))
+    r = oracle.run2d(pb, q, cfl=CFL[P], max_half_steps=9)
+    assert r.flags == 0
+    np.testing.assert_allclose(r.q, _transpose_state(P, r.q), rtol=0, atol=1e-13)
+
+
+@pytest.mark.parametrize("P", [1, 2])
+def test_riemann2d_first_config(P):
+    """The first 2D Riemann problem of Section 5.3 (four shocks) on a coarse
+    mesh, limited: positive density and pressure throughout, and the
+    configuration's symmetry about the diagonal x = y (states 2 and 4 are
+    mirror images) is kept with u and v exchanged."""
+    N = 24
+    q0 = inputs.riemann2d(1, P, N)
+    pb = oracle.Problem2D("euler", P, N, N, limiter=True, bc="transmissive", x_left=-1.0, x_right=1.0,
+                          y_left=-1.0, y_right=1.0)
+    r = oracle.run2d(pb, q0, cfl=CFL[P], t_end=0.2)
+    assert r.flags == 0 and r.t == 0.2
+    rho = r.q[0, 0]
+    assert np.all(rho > 0.0)
+    mirror = _transpose_state(P, r.q)
+    mirror[[1, 2]] = mirror[[2, 1]]
+    scale = np.abs(r.q).max(axis=(1, 2, 3), keepdims=True)
+    np.testing.assert_allclose(r.q / scale, mirror / scale, rtol=0, atol=1e-11)
