@@ -171,7 +171,9 @@ def time_2d(args):
     """The 2D half-step (Section 3): Burgers with the limiter, P = 3, on a
     2048 x 2048 periodic mesh of [0, 2]^2 with seeded sine modes; and the
     Euler isentropic vortex of Table 3, P = 3, 1024 x 1024 on [-5, 5]^2,
-    unlimited (LCCS) and with the rotated characteristic limiter (WCCS).
+    unlimited (LCCS) and with the rotated characteristic limiter (WCCS); the
+    first 2D Riemann problem of Section 5.3 with 1200 x 1200 intervals on
+    [-1, 1]^2, transmissive edges, limited, P = 3.
     Binary64, the library's default launch (row marching with prefetch).
     Algorithmic bytes per launch: every old cell read once and every new cell
     written once, nc * ndof doubles each; `traffic` is the measured HBM bytes
@@ -184,10 +186,14 @@ def time_2d(args):
              ("euler_vortex_P3", "euler", 3, args.n2d_euler, False, (-5.0, 5.0, -5.0, 5.0), 0.25,
               lambda: inputs.isentropic_vortex(3, args.n2d_euler)),
              ("euler_vortex_lim_P3", "euler", 3, args.n2d_euler, True, (-5.0, 5.0, -5.0, 5.0), 0.25,
-              lambda: inputs.isentropic_vortex(3, args.n2d_euler))]
+              lambda: inputs.isentropic_vortex(3, args.n2d_euler)),
+             ("riemann2d_1_lim_P3", "euler", 3, args.n2d_riemann, True, (-1.0, 1.0, -1.0, 1.0), 0.25,
+              lambda: inputs.riemann2d(1, 3, args.n2d_riemann))]
     for name, eq, P, N, lim, dom, cfl, make in cases:
         q0 = make()
-        s = binding.Solver2D(eq, P, N, N, limiter=lim, x_left=dom[0], x_right=dom[1], y_left=dom[2], y_right=dom[3])
+        bc = "transmissive" if name.startswith("riemann") else "periodic"
+        s = binding.Solver2D(eq, P, N, N, limiter=lim, x_left=dom[0], x_right=dom[1], y_left=dom[2], y_right=dom[3],
+                             bc=bc)
         s.write(q0)
         s.run(args.warmup2d, cfl)
         torch.cuda.synchronize()
@@ -198,21 +204,26 @@ def time_2d(args):
         launch_s = s.last_run_ms() / 1e3 / args.steps2d
         info = s.info()
         nc, nd = s.nc, s.nd
-        dofs = N * N * nc * nd * args.steps2d
-        bpl = 2.0 * N * N * nc * nd * 8
+        # cells per half-step: N^2 on both meshes (periodic); (N+1)^2 and N^2
+        # alternately (transmissive), averaged
+        cells = N * N if bc == "periodic" else 0.5 * ((N + 1) ** 2 + N * N)
+        dofs = cells * nc * nd * args.steps2d
+        bpl = 2.0 * cells * nc * nd * 8
         kernel = f"k2d_half_step_rows<{eq},P={P},{'limiter' if lim else 'no limiter'},prefetch>"
-        e = {"value": dofs / wall, "unit": "cell-DOF updates/s", "N": N, "P": P, "limiter": lim,
+        e = {"value": dofs / wall, "unit": "cell-DOF updates/s", "N": N, "P": P, "limiter": lim, "bc": bc,
              "cfl": cfl, "half_steps": args.steps2d, "kernel": kernel, "launch_us": launch_s * 1e6,
              "bytes_per_launch": bpl, "hbm_frac": bpl / launch_s / HBM_PEAK,
-             "traffic": measured_traffic(kernel, N, "2d"), "valid": bool((info.flags & 3) == 0)}
+             "traffic": measured_traffic(kernel + ("" if bc == "periodic" else ",transmissive"), N, "2d"),
+             "valid": bool((info.flags & 3) == 0)}
         s.close()
         if not args.no_cpu:
             import oracle
             pb = oracle.Problem2D(eq, P, N, N, limiter=lim, x_left=dom[0], x_right=dom[1], y_left=dom[2],
-                                  y_right=dom[3])
+                                  y_right=dom[3], bc=bc)
             t0 = time.perf_counter()
             r = oracle.run2d(pb, q0, cfl=cfl, max_half_steps=1)
             cw = time.perf_counter() - t0
+            # one half-step from parity 0: N x N new cells on either boundary
             e["cpu_baseline"] = {"value": N * N * nc * nd * r.half_steps / cw, "unit": "cell-DOF updates/s",
                                  "cores": 1, "kind": "oracle",
                                  "sample": f"first half-step of the same workload, FP64 oracle, single thread, "
@@ -338,6 +349,7 @@ def main():
     ap.add_argument("--no-2d", action="store_true", help="skip the 2D legs")
     ap.add_argument("--n2d", type=int, default=2048, help="2D Burgers mesh (n2d x n2d)")
     ap.add_argument("--n2d-euler", type=int, default=1024, help="2D Euler vortex mesh")
+    ap.add_argument("--n2d-riemann", type=int, default=1200, help="2D Riemann problem mesh (intervals per side)")
     ap.add_argument("--steps2d", type=int, default=240)
     ap.add_argument("--warmup2d", type=int, default=96)
     ap.add_argument("--seeds", default="0,1,2,3,4",

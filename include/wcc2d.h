@@ -2,9 +2,10 @@
  * schemes (Shen & Parsani, arXiv:2104.04347, Section 3 and Appendix B; the
  * 2D Euler step of Section 4) on gfx950.
  *
- * The library advances u_t + f(u)_x + g(u)_y = 0 (Eq. 2DHCL) on a periodic
- * rectangle [x_left, x_right] x [y_left, y_right] with Nx x Ny cells, on the
- * two space-time staggered Cartesian meshes of Section 3.1.  One half-step is
+ * The library advances u_t + f(u)_x + g(u)_y = 0 (Eq. 2DHCL) on a rectangle
+ * [x_left, x_right] x [y_left, y_right] cut into Nx x Ny intervals, periodic
+ * or with transmissive edges, on the two space-time staggered Cartesian
+ * meshes of Section 3.1.  One half-step is
  * one fused GPU kernel: trivariate Cauchy-Kovalewski expansion of every old
  * cell, quarter-cell averages (Eq. SubEq:2DCellAVGRU/RD/LU/LD) and half-edge
  * space-time flux averages (Eq. SubEq:2DFluxFU/FD/GR/GL) combined into the new
@@ -22,14 +23,19 @@
  *   (f = g = u^2/2), WCC_EULER (rho, rho u, rho v, rho e; gamma-law gas);
  *   limiter 0 gives the unlimited LCCS form, 1 the WCCS form.
  * - State layout at the boundary: host doubles indexed
- *   [c][d][j][i] = host[((c*ndof + d)*Ny + j)*Nx + i], ndof = (P+1)(P+2)/2,
+ *   [c][d][j][i] = host[((c*ndof + d)*ny + j)*nx + i] with nx x ny the cells
+ *   of the state's mesh (below), ndof = (P+1)(P+2)/2,
  *   with the DOFs u_{kx,ly} = dx^k dy^l d^{k+l}u/dx^k dy^l at the cell
  *   centre in "DOF order": total degree k+l ascending, then l ascending
  *   (d = (k+l)(k+l+1)/2 + l); d = 0 is the point value (Eq.
  *   2DPolynomial_Space).
  * - Meshes: dx = (x_right-x_left)/Nx, dy = (y_right-y_left)/Ny; parity 0
- *   centres (x_left + i dx, y_left + j dy), parity 1 shifted by (dx/2, dy/2);
- *   Nx x Ny cells on both (periodic).
+ *   centres (x_left + i dx, y_left + j dy), parity 1 shifted by (dx/2, dy/2).
+ *   WCC_BC_PERIODIC: nx x ny = Nx x Ny cells on both meshes, indices wrap.
+ *   WCC_BC_TRANSMISSIVE: parity 0 has the (Nx+1) x (Ny+1) cells centred at
+ *   the mesh points (the domain's edges and corners included), parity 1 the
+ *   Nx x Ny cells between them; the parents an edge cell of parity 0 lacks
+ *   are copies (all DOFs) of the adjacent parity-1 cell.
  * - Time step: dt = cfl / s_max with s_max the largest s_x/dx + s_y/dy over
  *   the current cell averages (s_x = |a|, |u| or |u|+c; s_y likewise), i.e.
  *   cfl is the CFL number of the half-step; clipped to t_end by wcc2d_advance.
@@ -57,14 +63,14 @@ typedef struct {
   double gamma;                               /* Euler, default 1.4 */
   double eps;                                 /* limiter epsilon, default 1e-40 (Section 3.2) */
   int32_t limiter;                            /* 0/1, default 1 */
-  int32_t reserved;
+  int32_t bc;                                 /* WCC_BC_PERIODIC (default) or WCC_BC_TRANSMISSIVE */
 } wcc2d_params;
 
 typedef struct {
   double t;             /* time of the current state */
   int32_t parity;       /* mesh of the current state */
   int32_t flags;        /* bit0 non-finite value, bit1 rho <= 0 or p <= 0 */
-  int64_t Nx, Ny;
+  int64_t Nx, Ny;       /* cells of the current mesh (see Meshes) */
   double dx, dy;
   int64_t half_steps;   /* half-steps taken since the last write */
   double s_max;         /* s_x/dx + s_y/dy of the current state */
@@ -74,9 +80,9 @@ typedef struct {
 int wcc2d_params_default(wcc2d_params* p);
 
 /* New context for equation (WCC_ADVECTION, WCC_BURGERS, WCC_EULER), degree
- * P in [0, WCC2D_PMAX], Nx, Ny >= 2 cells with Nx*Ny <= 2^28.  params may be
- * null (defaults).  Errors: WCC_EINVAL for bad sizes, enums or domain,
- * gamma <= 1 for Euler. */
+ * P in [0, WCC2D_PMAX], Nx, Ny >= 2 intervals with (Nx+1)*(Ny+1) <= 2^28.
+ * params may be null (defaults).  Errors: WCC_EINVAL for bad sizes, enums
+ * (equation, boundary) or domain, gamma <= 1 for Euler. */
 int wcc2d_create(int equation, int P, int64_t Nx, int64_t Ny, const wcc2d_params* params, wcc2d_ctx** out);
 
 /* Device bytes the caller must provide to wcc2d_bind: a control block, the
@@ -88,7 +94,7 @@ int wcc2d_workspace_bytes(const wcc2d_ctx* c, size_t* bytes);
  * Errors: WCC_EINVAL (null or misaligned), WCC_ESIZE (too small). */
 int wcc2d_bind(wcc2d_ctx* c, void* dev_ptr, size_t bytes, void* hip_stream);
 
-/* Copy a host state (layout above, Nx*Ny cells) onto mesh `parity` at time
+/* Copy a host state (layout above, the cells of mesh `parity`) onto that mesh at time
  * t and compute its wave-speed rate; synchronises the stream.  Errors:
  * WCC_ESTATE before bind, WCC_EINVAL, WCC_ENONFINITE (state kept). */
 int wcc2d_write_dofs(wcc2d_ctx* c, const double* host, int parity, double t);

@@ -135,7 +135,6 @@ class Problem:
         s.N = self.N
         s.bc = BCS[self.bc]
         s.limiter = 1 if self.limiter else 0
-        s.bc = BCS2D[self.bc]
         s.x_left = self.x_left
         s.x_right = self.x_right
         s.a = self.a

@@ -53,7 +53,7 @@ class wcc2d_params(ctypes.Structure):
         ("x_left", ctypes.c_double), ("x_right", ctypes.c_double),
         ("y_left", ctypes.c_double), ("y_right", ctypes.c_double),
         ("a", ctypes.c_double), ("b", ctypes.c_double), ("gamma", ctypes.c_double), ("eps", ctypes.c_double),
-        ("limiter", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("limiter", ctypes.c_int32), ("bc", ctypes.c_int32),
     ]
 
 
@@ -343,15 +343,18 @@ DOF2D_NOTE = "DOF order: k + l ascending, then l ascending; index (k+l)(k+l+1)/2
 
 
 class Solver2D:
-    """One 2D instance on a periodic rectangle: u_t + f(u)_x + g(u)_y = 0
-    advanced by the gfx950 2D half-step kernel.  States are numpy arrays of
-    shape (nc, ndof, Ny, Nx) in DOF order."""
+    """One 2D instance on a rectangle of Nx x Ny intervals, periodic or with
+    transmissive edges: u_t + f(u)_x + g(u)_y = 0 advanced by the gfx950 2D
+    half-step kernel.  States are numpy arrays of shape (nc, ndof, ny, nx) in
+    DOF order, nx x ny the cells of the state's mesh (`mesh_shape`)."""
 
     def __init__(self, equation: str, P: int, Nx: int, Ny: int, *, limiter: bool = True, x_left: float = 0.0,
                  x_right: float = 1.0, y_left: float = 0.0, y_right: float = 1.0, a: float = 1.0, b: float = 1.0,
-                 gamma: float = 1.4, eps: float = 1e-40, stream=None):
+                 gamma: float = 1.4, eps: float = 1e-40, bc: str = "periodic", stream=None):
         lib = load()
-        self.equation, self.P, self.Nx, self.Ny = equation, P, Nx, Ny
+        if bc not in ("periodic", "transmissive"):
+            raise ValueError(f"2D boundary {bc!r}: periodic or transmissive")
+        self.equation, self.P, self.Nx, self.Ny, self.bc = equation, P, Nx, Ny, bc
         self.nc = 4 if equation == "euler" else 1
         self.nd = (P + 1) * (P + 2) // 2
         p = wcc2d_params()
@@ -359,6 +362,7 @@ class Solver2D:
         p.x_left, p.x_right, p.y_left, p.y_right = x_left, x_right, y_left, y_right
         p.a, p.b, p.gamma, p.eps = a, b, gamma, eps
         p.limiter = 1 if limiter else 0
+        p.bc = BCS[bc]
         self.params = p
         h = ctypes.c_void_p()
         _check(lib.wcc2d_create(EQUATIONS[equation], P, Nx, Ny, ctypes.byref(p), ctypes.byref(h)), "wcc2d_create")
@@ -370,13 +374,18 @@ class Solver2D:
         _check(lib.wcc2d_bind(h, ctypes.c_void_p(self.workspace.data_ptr()), nb.value, ctypes.c_void_p(self.stream)),
                "wcc2d_bind", h, two_d=True)
 
+    def mesh_shape(self, parity: int) -> tuple:
+        e = 1 if (self.bc == "transmissive" and parity % 2 == 0) else 0
+        return (self.nc, self.nd, self.Ny + e, self.Nx + e)
+
     @property
     def shape(self):
-        return (self.nc, self.nd, self.Ny, self.Nx)
+        """State shape on the parity-0 mesh."""
+        return self.mesh_shape(0)
 
     def write(self, q: np.ndarray, parity: int = 0, t: float = 0.0) -> None:
         q = np.ascontiguousarray(q, dtype=np.float64)
-        assert q.shape == self.shape, (q.shape, self.shape)
+        assert q.shape == self.mesh_shape(parity), (q.shape, self.mesh_shape(parity))
         _check(load().wcc2d_write_dofs(self.h, _dptr(q), parity, float(t)), "wcc2d_write_dofs", self.h, two_d=True)
 
     def step(self, cfl: float = 0.0, dt_fixed: float = 0.0) -> None:
@@ -397,7 +406,7 @@ class Solver2D:
         return inf
 
     def read(self):
-        q = np.empty(self.shape, dtype=np.float64)
+        q = np.empty(self.mesh_shape(self.info().parity), dtype=np.float64)
         inf = wcc2d_state_info()
         _check(load().wcc2d_read_dofs(self.h, _dptr(q), q.size, ctypes.byref(inf)), "wcc2d_read_dofs", self.h,
                two_d=True)

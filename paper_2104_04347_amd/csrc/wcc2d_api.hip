@@ -36,6 +36,7 @@ inline size_t al256(size_t x) { return (x + 255) & ~size_t(255); }
 struct wcc2d_ctx {
   int eq = 0, P = 0, nc = 1, nd = 1;
   int64_t Nx = 0, Ny = 0, plane = 0;
+  int bc = WCC_BC_PERIODIC;
   wcc2d_params prm{};
   char* ws = nullptr;
   size_t ws_bytes = 0;
@@ -78,6 +79,12 @@ int fail2(wcc2d_ctx* c, int code, const char* fmt, ...) {
 double dx_of(const wcc2d_ctx* c) { return (c->prm.x_right - c->prm.x_left) / (double)c->Nx; }
 double dy_of(const wcc2d_ctx* c) { return (c->prm.y_right - c->prm.y_left) / (double)c->Ny; }
 
+// Cells of the mesh of this parity: Nx x Ny (periodic, and the staggered
+// transmissive mesh) or (Nx+1) x (Ny+1) (the transmissive mesh of the mesh
+// points).
+int64_t mesh_nx(const wcc2d_ctx* c, int parity) { return c->Nx + (c->bc == WCC_BC_PERIODIC || parity ? 0 : 1); }
+int64_t mesh_ny(const wcc2d_ctx* c, int parity) { return c->Ny + (c->bc == WCC_BC_PERIODIC || parity ? 0 : 1); }
+
 Step2Args args_for(const wcc2d_ctx* c, int parity, int slot, double dt_fixed) {
   Step2Args a{};
   a.q_old = c->q[parity];
@@ -85,6 +92,11 @@ Step2Args args_for(const wcc2d_ctx* c, int parity, int slot, double dt_fixed) {
   a.plane = c->plane;
   a.Nx = (int32_t)c->Nx;
   a.Ny = (int32_t)c->Ny;
+  a.nxo = (int32_t)mesh_nx(c, parity);
+  a.nyo = (int32_t)mesh_ny(c, parity);
+  a.nxn = (int32_t)mesh_nx(c, 1 - parity);
+  a.nyn = (int32_t)mesh_ny(c, 1 - parity);
+  a.periodic = c->bc == WCC_BC_PERIODIC ? 1 : 0;
   a.parity_old = parity;
   a.slot = slot;
   a.dx = dx_of(c);
@@ -102,10 +114,12 @@ Step2Args args_for(const wcc2d_ctx* c, int parity, int slot, double dt_fixed) {
   return a;
 }
 
-int blocks_for(wcc2d_ctx* c) {
+int blocks_for(wcc2d_ctx* c, int parity) {
   if (c->blocks > 0) return c->blocks;
-  // work units: 8 x 8 tiles (variant 0) or rows of 64-column strips
-  const int64_t units = c->variant >= 1 ? ((c->Nx + 62) / 63) * c->Ny : ((c->Nx + 6) / 7) * ((c->Ny + 6) / 7);
+  // work units over the new mesh: 8 x 8 tiles (variant 0) or rows of
+  // 64-column strips
+  const int64_t nx = mesh_nx(c, 1 - parity), ny = mesh_ny(c, 1 - parity);
+  const int64_t units = c->variant >= 1 ? ((nx + 62) / 63) * ny : ((nx + 6) / 7) * ((ny + 6) / 7);
   const int waves = c->threads / 64;
   int per_cu = 0;
   if (wcc2d::occupancy_half_step2(c->eq, c->P, c->prm.limiter != 0, c->variant, c->threads, &per_cu) != hipSuccess ||
@@ -117,7 +131,7 @@ int blocks_for(wcc2d_ctx* c) {
 
 int enqueue2(wcc2d_ctx* c, int parity, int slot, double dt_fixed, hipStream_t s) {
   hipError_t e = wcc2d::launch_half_step2(args_for(c, parity, slot, dt_fixed), c->eq, c->P, c->prm.limiter != 0,
-                                          c->variant, blocks_for(c), c->threads, s);
+                                          c->variant, blocks_for(c, parity), c->threads, s);
   if (e != hipSuccess) return fail2(c, WCC_EDEVICE, "2D half-step launch: %s", hipGetErrorString(e));
   return WCC_OK;
 }
@@ -233,9 +247,10 @@ int wcc2d_create(int equation, int P, int64_t Nx, int64_t Ny, const wcc2d_params
   if (!out) return WCC_EINVAL;
   *out = nullptr;
   if (equation < WCC_ADVECTION || equation > WCC_EULER || P < 0 || P > WCC2D_PMAX) return WCC_EINVAL;
-  if (Nx < 2 || Ny < 2 || Nx * Ny > ((int64_t)1 << 28)) return WCC_EINVAL;   // 32-bit byte offsets per plane
+  if (Nx < 2 || Ny < 2 || (Nx + 1) * (Ny + 1) > ((int64_t)1 << 28)) return WCC_EINVAL;   // 32-bit byte offsets
   wcc2d_params prm;
   if (params) prm = *params; else wcc2d_params_default(&prm);
+  if (prm.bc != WCC_BC_PERIODIC && prm.bc != WCC_BC_TRANSMISSIVE) return WCC_EINVAL;
   if (!(prm.x_right > prm.x_left) || !(prm.y_right > prm.y_left) || !(prm.eps >= 0.0)) return WCC_EINVAL;
   if (equation == WCC_EULER && !(prm.gamma > 1.0)) return WCC_EINVAL;
   wcc2d_ctx* c = new wcc2d_ctx();
@@ -245,7 +260,8 @@ int wcc2d_create(int equation, int P, int64_t Nx, int64_t Ny, const wcc2d_params
   c->nd = (P + 1) * (P + 2) / 2;
   c->Nx = Nx;
   c->Ny = Ny;
-  c->plane = (Nx * Ny + 63) / 64 * 64;
+  c->bc = prm.bc;
+  c->plane = (mesh_nx(c, 0) * mesh_ny(c, 0) + 63) / 64 * 64;
   c->prm = prm;
   int dev = 0;
   if (hipGetDevice(&dev) == hipSuccess) {
@@ -292,7 +308,7 @@ int wcc2d_write_dofs(wcc2d_ctx* c, const double* host, int parity, double t) {
   if (!c) return WCC_EINVAL;
   if (!c->bound) return fail2(c, WCC_ESTATE, "wcc2d_write_dofs before wcc2d_bind");
   if (!host || (parity != 0 && parity != 1) || !std::isfinite(t)) return fail2(c, WCC_EINVAL, "bad arguments");
-  const size_t cells = (size_t)(c->Nx * c->Ny);
+  const size_t cells = (size_t)(mesh_nx(c, parity) * mesh_ny(c, parity));
   for (int r = 0; r < c->nc * c->nd; ++r)
     HIPCHK2(c, hipMemcpyAsync(c->q[parity] + (size_t)r * c->plane, host + (size_t)r * cells, cells * 8,
                               hipMemcpyHostToDevice, c->stream));
@@ -385,7 +401,7 @@ int wcc2d_read_dofs(wcc2d_ctx* c, double* host, int64_t cap, wcc2d_state_info* i
   int rc = read_ctrl2(c, &h);
   if (rc) return rc;
   const int parity = parity_now(c);
-  const size_t cells = (size_t)(c->Nx * c->Ny);
+  const size_t cells = (size_t)(mesh_nx(c, parity) * mesh_ny(c, parity));
   if (host) {
     if (cap < (int64_t)(c->nc * c->nd * cells)) return fail2(c, WCC_ESIZE, "host buffer too small");
     for (int r = 0; r < c->nc * c->nd; ++r)
@@ -398,8 +414,8 @@ int wcc2d_read_dofs(wcc2d_ctx* c, double* host, int64_t cap, wcc2d_state_info* i
     info->t = h.t[s];
     info->parity = parity;
     info->flags = (int32_t)h.flags[s];
-    info->Nx = c->Nx;
-    info->Ny = c->Ny;
+    info->Nx = mesh_nx(c, parity);
+    info->Ny = mesh_ny(c, parity);
     info->dx = dx_of(c);
     info->dy = dy_of(c);
     info->half_steps = c->steps;

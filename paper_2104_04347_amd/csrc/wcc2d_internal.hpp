@@ -13,8 +13,11 @@ namespace wcc2d {
 struct Step2Args {
   const double* q_old;    // state of the old mesh: planes [c][dof], index j*Nx + i
   double* q_new;
-  int64_t plane;          // doubles per plane (Nx*Ny rounded up to 64)
-  int32_t Nx, Ny;
+  int64_t plane;          // doubles per plane (cells of the larger mesh rounded up to 64)
+  int32_t Nx, Ny;         // mesh intervals (dx = domain width / Nx)
+  int32_t nxo, nyo;       // cells of the old mesh (row width nxo)
+  int32_t nxn, nyn;       // cells of the new mesh
+  int32_t periodic;       // 1: indices wrap; 0: transmissive, indices clamp to the edge cell
   int32_t parity_old;     // 0: original -> staggered mesh, 1: back
   int32_t slot;           // ring slot of this launch
   double dx, dy;

@@ -29,6 +29,13 @@ __device__ __forceinline__ int wrap(int i, int n) {
   return r < 0 ? r + n : r;
 }
 
+// Old-mesh index of a parent: wrapped (periodic) or clamped to the edge cell
+// (transmissive ghosts are copies of the adjacent cell, Section 3.1 meshes).
+__device__ __forceinline__ int map_idx(int i, int n, int periodic) {
+  if (periodic) return wrap(i, n);
+  return i < 0 ? 0 : (i >= n ? n - 1 : i);
+}
+
 // One component's parent data at a lane, as the new cell uses it: the
 // quarter-average sum h and the flux differences fx, gy of Eq. 2DIntegral
 // (grouped as the oracle groups them) and the vertex values of the four
@@ -120,7 +127,7 @@ __device__ __forceinline__ void new_cell2(const Step2Args& a, Gather&& gather, b
 template <int EQ, int P>
 __device__ __forceinline__ void load_old(const Step2Args& a, int i, int j, double (&q)[ncomp<EQ>()][ndof(P)]) {
   constexpr int NC = ncomp<EQ>(), ND = ndof(P);
-  const uint32_t cell = (uint32_t)(j * a.Nx + i);
+  const uint32_t cell = (uint32_t)(j * a.nxo + i);
 #pragma unroll
   for (int c = 0; c < NC; ++c)
 #pragma unroll
@@ -149,9 +156,10 @@ __device__ __forceinline__ void run_tile2(const Step2Args& a, int tile, int tile
   const int lx = lane & 7, ly = lane >> 3;
   const int off = a.parity_old == 0 ? 0 : -1;
   Old2<EQ, P> o;
-  old_of<EQ, P>(a, wrap(7 * tx + lx + off, a.Nx), wrap(7 * ty + ly + off, a.Ny), nlx, nly, o);
+  old_of<EQ, P>(a, map_idx(7 * tx + lx + off, a.nxo, a.periodic), map_idx(7 * ty + ly + off, a.nyo, a.periodic), nlx,
+                nly, o);
   const int ni = 7 * tx + lx, nj = 7 * ty + ly;
-  const bool mine = lx < 7 && ly < 7 && ni < a.Nx && nj < a.Ny;
+  const bool mine = lx < 7 && ly < 7 && ni < a.nxn && nj < a.nyn;
   auto gather = [&](int c, Par2<P>& g) {
     const double B_RD = __shfl(o.RD[c], lane + 8, 64), B_fD = __shfl(o.fD[c], lane + 8, 64),
                  B_gR = __shfl(o.gR[c], lane + 8, 64);
@@ -168,14 +176,14 @@ __device__ __forceinline__ void run_tile2(const Step2Args& a, int tile, int tile
     }
     combine<P>(g, o.RU[c], B_RD, C_LU, E_LD, o.fU[c], C_fU, B_fD, E_fD, o.gR[c], B_gR, C_gL, E_gL);
   };
-  new_cell2<EQ, P, LIM>(a, gather, mine, (uint32_t)(nj * a.Nx + ni), hx, hy, smax, flags);
+  new_cell2<EQ, P, LIM>(a, gather, mine, (uint32_t)(nj * a.nxn + ni), hx, hy, smax, flags);
 }
 
 template <int EQ, int P, bool LIM>
 __global__ __launch_bounds__(256) void k2d_half_step(const Step2Args a) {
   const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6),
             nw = blockDim.x >> 6;
-  const int tiles_x = (a.Nx + 6) / 7, tiles_y = (a.Ny + 6) / 7;
+  const int tiles_x = (a.nxn + 6) / 7, tiles_y = (a.nyn + 6) / 7;
   const int tiles = tiles_x * tiles_y;
   const int per_block = (tiles + (int)gridDim.x - 1) / (int)gridDim.x;
   const int t_begin = (int)blockIdx.x * per_block;
@@ -229,7 +237,7 @@ __global__ __launch_bounds__(256) void k2d_half_step_rows(const Step2Args a) {
   const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6),
             nw = blockDim.x >> 6;
   RowCarry<EQ, P>& carry = carry_all[wave];
-  const int strips = (a.Nx + 62) / 63, rows = a.Ny;
+  const int strips = (a.nxn + 62) / 63, rows = a.nyn;
   const int64_t units = (int64_t)strips * rows, waves = (int64_t)gridDim.x * nw;
   const int64_t gw = (int64_t)blockIdx.x * nw + wave;
   const int u_begin = (int)(gw * units / waves), u_end = (int)((gw + 1) * units / waves);
@@ -243,15 +251,15 @@ __global__ __launch_bounds__(256) void k2d_half_step_rows(const Step2Args a) {
   double qn[NC][ND];
   if (PF && u_begin < u_end) {
     const int sx = u_begin / rows, r = u_begin - sx * rows;
-    load_old<EQ, P>(a, wrap(63 * sx + lane + off, a.Nx), wrap(r + 1 + off, a.Ny), qn);
+    load_old<EQ, P>(a, map_idx(63 * sx + lane + off, a.nxo, a.periodic), map_idx(r + 1 + off, a.nyo, a.periodic), qn);
   }
   for (int u = u_begin; u < u_end; ++u) {
     const int sx = u / rows, r = u - sx * rows;
-    const int i = wrap(63 * sx + lane + off, a.Nx);
+    const int i = map_idx(63 * sx + lane + off, a.nxo, a.periodic);
     if (u == u_begin || r == 0) {
       // lower parents of new row r: the old row below, expanded afresh
       Old2<EQ, P> o;
-      old_of<EQ, P>(a, i, wrap(r + off, a.Ny), nlx, nly, o);
+      old_of<EQ, P>(a, i, map_idx(r + off, a.nyo, a.periodic), nlx, nly, o);
 #pragma unroll
       for (int c = 0; c < NC; ++c) put_carry<EQ, P>(carry, c, lane, o);
     }
@@ -263,16 +271,17 @@ __global__ __launch_bounds__(256) void k2d_half_step_rows(const Step2Args a) {
         for (int d = 0; d < ND; ++d) q[c][d] = qn[c][d];
       if (u + 1 < u_end) {
         const int sx2 = (u + 1) / rows, r2 = u + 1 - sx2 * rows;
-        load_old<EQ, P>(a, wrap(63 * sx2 + lane + off, a.Nx), wrap(r2 + 1 + off, a.Ny), qn);
+        load_old<EQ, P>(a, map_idx(63 * sx2 + lane + off, a.nxo, a.periodic), map_idx(r2 + 1 + off, a.nyo, a.periodic),
+                        qn);
       }
       __builtin_amdgcn_sched_barrier(0);
     } else {
-      load_old<EQ, P>(a, i, wrap(r + 1 + off, a.Ny), q);
+      load_old<EQ, P>(a, i, map_idx(r + 1 + off, a.nyo, a.periodic), q);
     }
     Old2<EQ, P> o;
     old_cell2<EQ, P>(q, nlx, nly, a.ph, o);
     const int ni = 63 * sx + lane;
-    const bool mine = lane < 63 && ni < a.Nx;
+    const bool mine = lane < 63 && ni < a.nxn;
     auto gather = [&](int c, Par2<P>& g) {
       // the lane's own slot: read the row below, then leave this row for the
       // next unit
@@ -293,7 +302,7 @@ __global__ __launch_bounds__(256) void k2d_half_step_rows(const Step2Args a) {
       }
       combine<P>(g, A_RU, o.RD[c], C_LU, E_LD, A_fU, C_fU, o.fD[c], E_fD, A_gR, o.gR[c], C_gL, E_gL);
     };
-    new_cell2<EQ, P, LIM>(a, gather, mine, (uint32_t)(r * a.Nx + ni), hx, hy, smax, flags);
+    new_cell2<EQ, P, LIM>(a, gather, mine, (uint32_t)(r * a.nxn + ni), hx, hy, smax, flags);
   }
   wcc::publish(a.ctrl, a.parts, a.slot, smax, flags);
 }
@@ -304,7 +313,7 @@ __global__ __launch_bounds__(256) void k2d_state_speed(const Step2Args a) {
   constexpr int NC = ncomp<EQ>(), ND = ndof(P);
   double smax = 0.0;
   unsigned flags = 0u;
-  const int64_t n = (int64_t)a.Nx * a.Ny;
+  const int64_t n = (int64_t)a.nxo * a.nyo;
   for (int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; o < n; o += (int64_t)gridDim.x * blockDim.x) {
     double ab[NC];
     bool ok = true;

@@ -163,6 +163,63 @@ def test_euler_modes_limited_bitwise(P, variant):
     assert_bitwise(q, info, r, f"limited modes P={P}")
 
 
+def oracle_run_t(eq, P, Nx, Ny, q0, dom, parity=0, **kw):
+    pb = oracle.Problem2D(eq, P, Nx, Ny, limiter=True, bc="transmissive", x_left=dom[0], x_right=dom[1],
+                          y_left=dom[2], y_right=dom[3], a=0.7, b=-0.4)
+    return oracle.run2d(pb, q0, parity=parity, **kw)
+
+
+def gpu_run_t(eq, P, Nx, Ny, q0, dom, variant, parity=0, half_steps=None, t_end=None, cfl=None):
+    s = binding.Solver2D(eq, P, Nx, Ny, limiter=True, bc="transmissive", x_left=dom[0], x_right=dom[1],
+                         y_left=dom[2], y_right=dom[3], a=0.7, b=-0.4)
+    try:
+        s.set_launch(0, 0, variant)
+        s.write(q0, parity=parity)
+        if t_end is not None:
+            s.advance(t_end, cfl)
+        else:
+            s.run(half_steps, cfl)
+        return s.read()
+    finally:
+        s.close()
+
+
+@pytest.mark.parametrize("variant", VARIANTS)
+@pytest.mark.parametrize("eq", ["advection", "burgers"])
+@pytest.mark.parametrize("P", [1, 2, 3])
+@pytest.mark.parametrize("parity", [0, 1])
+def test_transmissive_scalar_bitwise(eq, P, parity, variant):
+    """Transmissive edges (Section 3.1 meshes): (Nx+1) x (Ny+1) mesh-point
+    cells on parity 0, Nx x Ny between them; 70 x 23 intervals (two ragged
+    strips), written on either mesh, 13 half-steps."""
+    Nx, Ny = 70, 23
+    dom = (0.0, 2.0, 0.0, 2.0)
+    fn = inputs.modes2d(5)
+    X, Y = inputs.centers2d(*dom, Nx, Ny, parity, "transmissive")
+    q0 = np.zeros((1, inputs.ndof2d(P)) + X.shape)
+    for k, l in inputs.dof_pairs(P):
+        q0[0, inputs.dof2d(k, l)] = (2.0 / Nx) ** k * (2.0 / Ny) ** l * fn.deriv(X, Y, k, l)
+    q, info = gpu_run_t(eq, P, Nx, Ny, q0, dom, variant, parity=parity, half_steps=13, cfl=CFL[P])
+    r = oracle_run_t(eq, P, Nx, Ny, q0, dom, parity=parity, cfl=CFL[P], max_half_steps=13)
+    assert q.shape == r.q.shape
+    assert_bitwise(q, info, r, f"transmissive {eq} P={P} parity={parity} variant={variant}")
+
+
+@pytest.mark.parametrize("variant", VARIANTS)
+@pytest.mark.parametrize("config", [1, 2])
+@pytest.mark.parametrize("P", [1, 2, 3])
+def test_riemann2d_bitwise(config, P, variant):
+    """The 2D Riemann problems of Section 5.3 on a coarse 40 x 40 mesh,
+    limited Euler with transmissive edges, to t = 0.1."""
+    N = 40
+    dom = (-1.0, 1.0, -1.0, 1.0)
+    q0 = inputs.riemann2d(config, P, N)
+    q, info = gpu_run_t("euler", P, N, N, q0, dom, variant, t_end=0.1, cfl=CFL[P])
+    r = oracle_run_t("euler", P, N, N, q0, dom, t_end=0.1, cfl=CFL[P])
+    assert info.t == 0.1
+    assert_bitwise(q, info, r, f"Riemann {config} P={P} variant={variant}")
+
+
 def test_2d_errors():
     s = binding.Solver2D("burgers", 2, 16, 16)
     with pytest.raises(binding.WccError):
