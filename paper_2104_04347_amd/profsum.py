@@ -10,7 +10,7 @@ Measurement tooling; runs on any host, no GPU needed.
       per-kernel mean / min / max of every counter of a --pmc run
 
   python -m paper_2104_04347_amd.profsum traffic FETCH_DB WRITE_DB --kernel SUBSTR
-          --key NAME --N N --copy-mib M [--sources 1d|2d] [--out profiles/traffic.json]
+          --key NAME --N N --copy-mib M [--sources 1d|2d] [--dispatches A:B] [--out profiles/traffic.json]
       HBM bytes per dispatch of the kernel whose name contains SUBSTR, from a
       FETCH_SIZE run and a WRITE_SIZE run (both in KiB per dispatch), each
       scaled by what the same counter reads for the runtime's device-to-device
@@ -67,7 +67,8 @@ def counter_values(db: str) -> dict:
     """{kernel name: {counter: [value per dispatch]}}"""
     con = sqlite3.connect(db)
     agg: dict = collections.defaultdict(lambda: collections.defaultdict(list))
-    for name, counter, value in con.execute("select kernel_name, counter_name, value from counters_collection"):
+    for name, counter, value in con.execute("select kernel_name, counter_name, value from counters_collection "
+                                            "order by dispatch_id"):
         agg[name][counter].append(float(value))
     return agg
 
@@ -81,12 +82,12 @@ def counters_table(db: str) -> str:
     return "\n".join(out)
 
 
-def _one(db: str, counter: str, match: str):
+def _one(db: str, counter: str, match: str, select: slice = slice(None)):
     agg = counter_values(db)
     ks = [k for k in agg if match in k]
     if len(ks) != 1:
         raise SystemExit(f"{db}: {len(ks)} kernels match {match!r}: {ks}")
-    vals = agg[ks[0]].get(counter)
+    vals = (agg[ks[0]].get(counter) or [])[select]
     if not vals:
         raise SystemExit(f"{db}: no {counter} values for {ks[0]}")
     copies = agg.get(COPY_KERNEL, {}).get(counter)
@@ -96,9 +97,9 @@ def _one(db: str, counter: str, match: str):
 
 
 def traffic(fetch_db: str, write_db: str, match: str, key: str, N: int, copy_mib: int, out: str | None,
-            sources: str = "1d") -> dict:
-    name, fv, fcopy = _one(fetch_db, "FETCH_SIZE", match)
-    _, wv, wcopy = _one(write_db, "WRITE_SIZE", match)
+            sources: str = "1d", select: slice = slice(None)) -> dict:
+    name, fv, fcopy = _one(fetch_db, "FETCH_SIZE", match, select)
+    _, wv, wcopy = _one(write_db, "WRITE_SIZE", match, select)
     copy_kib = copy_mib * 1024.0
     ff, wf = copy_kib / fcopy, copy_kib / wcopy
     rec = {
@@ -145,6 +146,8 @@ def main(argv=None) -> None:
     r.add_argument("--N", type=int, required=True)
     r.add_argument("--copy-mib", type=int, required=True)
     r.add_argument("--sources", choices=("1d", "2d"), default="1d")
+    r.add_argument("--dispatches", default=":",
+                   help="A:B, the kernel's dispatches A to B-1 in launch order (a kernel run by several legs)")
     r.add_argument("--out")
     a = ap.parse_args(argv)
     if a.cmd == "trace":
@@ -152,8 +155,9 @@ def main(argv=None) -> None:
     elif a.cmd == "counters":
         print(counters_table(a.db))
     else:
-        json.dump(traffic(a.fetch_db, a.write_db, a.kernel, a.key, a.N, a.copy_mib, a.out, a.sources), sys.stdout,
-                  indent=1)
+        lo, hi = (int(v) if v else None for v in a.dispatches.split(":"))
+        json.dump(traffic(a.fetch_db, a.write_db, a.kernel, a.key, a.N, a.copy_mib, a.out, a.sources, slice(lo, hi)),
+                  sys.stdout, indent=1)
         print()
 
 
