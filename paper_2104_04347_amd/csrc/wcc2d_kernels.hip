@@ -4,10 +4,10 @@
 // Two work decompositions with identical results (the launch variant):
 // 8 x 8 wave tiles exchanged by shuffles, and 64-column strips walked row by
 // row with a one-row carry in LDS, with or without prefetch of the next row
-// (described at each kernel).  The time step
-// comes from the same device-side ring as the 1D kernels (dt = cfl / smax
-// with smax the largest s_x/dx + s_y/dy of the previous step's new
-// averages), reduced through 64 partial slots.
+// (described at each kernel).  The time step comes from the same device-side
+// ring as the 1D kernels (dt = cfl / smax with smax the largest
+// s_x/dx + s_y/dy of the previous step's new averages), reduced through 64
+// partial slots.
 #include <hip/hip_runtime.h>
 
 #include "wcc2d_cell.hpp"
@@ -38,7 +38,8 @@ __device__ __forceinline__ int map_idx(int i, int n, int periodic) {
 
 // One component's parent data at a lane, as the new cell uses it: the
 // quarter-average sum h and the flux differences fx, gy of Eq. 2DIntegral
-// (grouped as the oracle groups them) and the vertex values of the four
+// (grouped per pair of opposite half-edges, so that data uniform in the
+// transverse direction cancel exactly) and the vertex values of the four
 // parents, A lower-left, B upper-left, C lower-right, E upper-right.
 template <int P>
 struct Par2 {

@@ -16,8 +16,8 @@ Measurement tooling; runs on any host, no GPU needed.
       scaled by what the same counter reads for the runtime's device-to-device
       copy of M MiB profiled in the same run (the largest copy dispatch).  The
       record is keyed by NAME and stamped with the SHA-256 of the kernel
-      sources (the 1D or the 2D half-step's), so that a later kernel change
-      invalidates it.
+      sources' code (the 1D or the 2D half-step's, comments removed), so that
+      a later kernel change invalidates it.
 """
 from __future__ import annotations
 
@@ -26,6 +26,7 @@ import collections
 import hashlib
 import json
 import os
+import re
 import sqlite3
 import statistics
 import sys
@@ -40,12 +41,25 @@ KERNEL_SOURCES = ("wcc_cell.hpp", "wcc_internal.hpp", "wcc_kernels.hip", "wcc_ti
 KERNEL_SOURCES_2D = ("wcc2d_cell.hpp", "wcc2d_internal.hpp", "wcc2d_kernels.hip", "wcc_internal.hpp", "wcc_tile.hpp")
 
 
-def kernel_source_hash(sources: str = "1d") -> str:
-    """SHA-256 over the sources of the 1D (or 2D) half-step kernel."""
+def code_only(text: str) -> str:
+    """C++ source without comments, trailing blanks and blank lines (string
+    literals in these sources hold no comment markers)."""
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", "", text)
+    return "\n".join(line.rstrip() for line in text.splitlines() if line.strip())
+
+
+def kernel_source_hash(sources: str = "1d", read=None) -> str:
+    """SHA-256 over the code (comments removed) of the sources of the 1D (or
+    2D) half-step kernel.  `read(name)` supplies a file's text (default: the
+    working tree)."""
+    if read is None:
+        def read(name):
+            with open(os.path.join(CSRC, name)) as f:
+                return f.read()
     h = hashlib.sha256()
     for name in (KERNEL_SOURCES if sources == "1d" else KERNEL_SOURCES_2D):
-        with open(os.path.join(CSRC, name), "rb") as f:
-            h.update(name.encode() + b"\0" + f.read())
+        h.update(name.encode() + b"\0" + code_only(read(name)).encode())
     return h.hexdigest()
 
 
