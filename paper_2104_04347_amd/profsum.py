@@ -42,11 +42,12 @@ KERNEL_SOURCES_2D = ("wcc2d_cell.hpp", "wcc2d_internal.hpp", "wcc2d_kernels.hip"
 
 
 def code_only(text: str) -> str:
-    """C++ source without comments, trailing blanks and blank lines (string
-    literals in these sources hold no comment markers)."""
+    """C++ source without comments and blank lines, runs of blanks within a
+    line made one (string literals in these sources hold no comment markers
+    and no runs of blanks)."""
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
     text = re.sub(r"//[^\n]*", "", text)
-    return "\n".join(line.rstrip() for line in text.splitlines() if line.strip())
+    return "\n".join(" ".join(line.split()) for line in text.splitlines() if line.strip())
 
 
 def kernel_source_hash(sources: str = "1d", read=None) -> str:

@@ -1,0 +1,115 @@
+"""Host logic around the kernels (no GPU): the benchmark's bookkeeping, the
+rocprofv3 summaries and counter record, the autotuner's cache keys."""
+import json
+import os
+import sqlite3
+
+import numpy as np
+import pytest
+
+import bench
+from paper_2104_04347_amd import autotune, profsum
+
+
+def test_cells_updated():
+    assert bench.cells_updated(100, "periodic", 0, 7) == 700
+    # transmissive: N new cells from the original mesh, N + 1 back
+    assert bench.cells_updated(100, "transmissive", 0, 4) == 100 + 101 + 100 + 101
+    assert bench.cells_updated(100, "transmissive", 1, 3) == 101 + 100 + 101
+
+
+def test_bytes_per_launch():
+    # Euler P = 3: binary64 96 B per cell, FP32-mixed 3 x (8 + 12) = 60 B
+    assert bench.bytes_per_launch(1 << 20, 3, 3, "fp64") == (2 * (1 << 20) + 1) * 96
+    assert bench.bytes_per_launch(1 << 20, 3, 3, "fp32_mixed") == (2 * (1 << 20) + 1) * 60
+
+
+def test_code_only_ignores_comments():
+    a = "int f(int x) {  // doubles x\n  /* a\n block */ return 2 * x;\n}\n"
+    b = "int f(int x) {\n\n  return 2 * x;   \n}"
+    assert profsum.code_only(a) == profsum.code_only(b)
+    assert profsum.code_only(a) != profsum.code_only(a.replace("2 * x", "3 * x"))
+
+
+def test_source_hash_follows_code_not_comments():
+    real = profsum.kernel_source_hash("2d")
+    texts = {n: open(os.path.join(profsum.CSRC, n)).read() for n in profsum.KERNEL_SOURCES_2D}
+    commented = dict(texts)
+    commented["wcc2d_kernels.hip"] = "// a new comment\n" + texts["wcc2d_kernels.hip"]
+    assert profsum.kernel_source_hash("2d", commented.__getitem__) == real
+    changed = dict(texts)
+    changed["wcc2d_kernels.hip"] = texts["wcc2d_kernels.hip"].replace("0.25 *", "0.5 *", 1)
+    assert profsum.kernel_source_hash("2d", changed.__getitem__) != real
+    assert profsum.kernel_source_hash("1d") != real
+
+
+def _fake_db(path, rows):
+    con = sqlite3.connect(path)
+    con.execute("create table counters_collection (dispatch_id integer, kernel_name text, counter_name text, "
+                "value real)")
+    con.executemany("insert into counters_collection values (?, ?, ?, ?)", rows)
+    con.commit()
+    con.close()
+
+
+def test_traffic_scaling_and_dispatch_selection(tmp_path, monkeypatch):
+    """FETCH_SIZE and WRITE_SIZE in KiB per dispatch, scaled by what the
+    counter reads for a copy of known size in the same run; a kernel shared
+    by two legs is split by dispatch order."""
+    k, copy = "void k2d<2, 3>(args)", profsum.COPY_KERNEL
+    fetch = [(1, copy, "FETCH_SIZE", 262144.0)]                      # a 512 MiB copy reads as half
+    fetch += [(10 + i, k, "FETCH_SIZE", 1000.0) for i in range(3)]
+    fetch += [(20 + i, k, "FETCH_SIZE", 3000.0) for i in range(3)]
+    write = [(1, copy, "WRITE_SIZE", 524288.0)]
+    write += [(10 + i, k, "WRITE_SIZE", 800.0) for i in range(3)] + [(20 + i, k, "WRITE_SIZE", 900.0) for i in range(3)]
+    _fake_db(tmp_path / "f.db", fetch)
+    _fake_db(tmp_path / "w.db", write)
+    out = tmp_path / "traffic.json"
+    rec = profsum.traffic(str(tmp_path / "f.db"), str(tmp_path / "w.db"), "k2d<2, 3>", "leg2", 64, 512, str(out),
+                          "2d", slice(3, 6))
+    assert rec["fetch_factor"] == 2.0 and rec["write_factor"] == 1.0
+    assert rec["fetch_bytes"] == 3000.0 * 1024 * 2 and rec["write_bytes"] == 900.0 * 1024
+    assert rec["dispatches"] == [3, 3] and rec["source_sha256"] == profsum.kernel_source_hash("2d")
+    assert json.load(open(out))["leg2"]["N"] == 64
+    # the benchmark reads such a record only for the same code and size
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    (tmp_path / "profiles").mkdir()
+    (tmp_path / "profiles" / "traffic.json").write_text(out.read_text())
+    assert bench.measured_traffic("leg2", 64, "2d") == rec["fetch_bytes"] + rec["write_bytes"]
+    assert bench.measured_traffic("leg2", 65, "2d") is None
+    assert bench.measured_traffic("leg2", 64, "1d") is None
+
+
+def test_committed_records_match_the_sources():
+    """The committed counter record belongs to the kernels as they are."""
+    rec = json.load(open(os.path.join(bench.ROOT, "profiles", "traffic.json")))
+    assert rec, "no records"
+    for key, e in rec.items():
+        assert e["source_sha256"] == profsum.kernel_source_hash(e.get("sources", "1d")), key
+        assert bench.measured_traffic(key, e["N"], e.get("sources", "1d")) > 0
+
+
+def test_autotune_keys():
+    assert autotune.key_single("euler", 3, 1 << 20, "fp64", True) == "single/euler/P3/fp64/lim/N2^20"
+    assert autotune.key_single("euler", 3, (1 << 20) + 5, "fp64", True) == "single/euler/P3/fp64/lim/N2^20"
+    assert autotune.key_single("burgers", 2, 3000, "fp32_mixed", False) == "single/burgers/P2/fp32_mixed/nolim/N2^11"
+
+
+def test_autotune_cache_roundtrip(tmp_path, monkeypatch):
+    monkeypatch.setenv("WCC_AUTOTUNE_CACHE", str(tmp_path / "sub" / "cache.json"))
+    assert autotune._load_cache() == {}
+    autotune._save_cache({"k": {"threads": 128}})
+    assert autotune._load_cache() == {"k": {"threads": 128}}
+    # an unwritable location only costs a re-tune
+    monkeypatch.setenv("WCC_AUTOTUNE_CACHE", "/proc/no/such/dir/cache.json")
+    autotune._save_cache({"k": 1})
+    assert autotune._load_cache() == {}
+
+
+def test_gpu_count_guard():
+    """bench.py measures one GPU and says so for any other count."""
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(bench.ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2 and "one GPU" in r.stderr
