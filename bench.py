@@ -160,10 +160,14 @@ def time_batch(args):
         flags |= bt.read(b)[1].flags & 3
     cells = int(np.sum(spec.N)) * args.batch_steps          # ~N per half-step per instance
     dofs = int(np.sum(spec.N * 3 * (spec.P + 1))) * args.batch_steps
+    # algorithmic bytes of one half-step of every instance (old + new cells)
+    bph = sum(bytes_per_launch(int(n), int(p), 3, "fp32_mixed") for n, p in zip(spec.N, spec.P))
+    gbs = bph * args.batch_steps / (ms / 1e3) / 1e9
     bt.close()
     return dict(value=spec.P.size / wall, unit="solves/s", instances=int(spec.P.size),
                 half_steps_each=args.batch_steps, wall_s=wall, event_ms=ms, cell_dof_per_s=dofs / wall,
-                total_cells=int(np.sum(spec.N)), cells_per_s=cells / wall, flags=int(flags),
+                total_cells=int(np.sum(spec.N)), cells_per_s=cells / wall, bytes_per_half_step=bph,
+                gbs=round(gbs, 1), hbm_frac=round(gbs * 1e9 / HBM_PEAK, 4), flags=int(flags),
                 schedule=sched or "default")
 
 
