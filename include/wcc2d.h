@@ -4,8 +4,8 @@
  *
  * The library advances u_t + f(u)_x + g(u)_y = 0 (Eq. 2DHCL) on a rectangle
  * [x_left, x_right] x [y_left, y_right] cut into Nx x Ny intervals, periodic
- * or with transmissive edges, on the two space-time staggered Cartesian
- * meshes of Section 3.1.  One half-step is
+ * or with transmissive edges in each direction, on the two space-time
+ * staggered Cartesian meshes of Section 3.1.  One half-step is
  * one fused GPU kernel: trivariate Cauchy-Kovalewski expansion of every old
  * cell, quarter-cell averages (Eq. SubEq:2DCellAVGRU/RD/LU/LD) and half-edge
  * space-time flux averages (Eq. SubEq:2DFluxFU/FD/GR/GL) combined into the new
@@ -31,11 +31,12 @@
  *   2DPolynomial_Space).
  * - Meshes: dx = (x_right-x_left)/Nx, dy = (y_right-y_left)/Ny; parity 0
  *   centres (x_left + i dx, y_left + j dy), parity 1 shifted by (dx/2, dy/2).
- *   WCC_BC_PERIODIC: nx x ny = Nx x Ny cells on both meshes, indices wrap.
- *   WCC_BC_TRANSMISSIVE: parity 0 has the (Nx+1) x (Ny+1) cells centred at
- *   the mesh points (the domain's edges and corners included), parity 1 the
- *   Nx x Ny cells between them; the parents an edge cell of parity 0 lacks
- *   are copies (all DOFs) of the adjacent parity-1 cell.
+ *   Per direction (bc for x, bc_y for y): WCC_BC_PERIODIC, N cells on both
+ *   meshes, indices wrap; WCC_BC_TRANSMISSIVE, parity 0 has the N+1 cells
+ *   centred at the mesh points (the domain's edges included), parity 1 the N
+ *   cells between them, and the parents an edge cell of parity 0 lacks are
+ *   copies (all DOFs) of the adjacent parity-1 cell (corners likewise).
+ *   nx = Nx or Nx+1 and ny = Ny or Ny+1 accordingly.
  * - Time step: dt = cfl / s_max with s_max the largest s_x/dx + s_y/dy over
  *   the current cell averages (s_x = |a|, |u| or |u|+c; s_y likewise), i.e.
  *   cfl is the CFL number of the half-step; clipped to t_end by wcc2d_advance.
@@ -63,7 +64,9 @@ typedef struct {
   double gamma;                               /* Euler, default 1.4 */
   double eps;                                 /* limiter epsilon, default 1e-40 (Section 3.2) */
   int32_t limiter;                            /* 0/1, default 1 */
-  int32_t bc;                                 /* WCC_BC_PERIODIC (default) or WCC_BC_TRANSMISSIVE */
+  int32_t bc;                                 /* x edges: WCC_BC_PERIODIC (default) or WCC_BC_TRANSMISSIVE */
+  int32_t bc_y;                               /* y edges: likewise; -1 (default): as bc */
+  int32_t reserved;
 } wcc2d_params;
 
 typedef struct {

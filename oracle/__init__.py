@@ -110,7 +110,7 @@ class Problem:
     equation: str
     P: int
     N: int
-    bc: str = "periodic"
+    bc: object = "periodic"     # "periodic", "transmissive" or a pair (x, y) of them
     limiter: bool = False
     x_left: float = 0.0
     x_right: float = 1.0
@@ -298,6 +298,8 @@ class _Problem2D(ctypes.Structure):
         ("Ny", ctypes.c_int64),
         ("limiter", ctypes.c_int32),
         ("bc", ctypes.c_int32),
+        ("bc_y", ctypes.c_int32),
+        ("pad2", ctypes.c_int32),
         ("x_left", ctypes.c_double),
         ("x_right", ctypes.c_double),
         ("y_left", ctypes.c_double),
@@ -351,10 +353,11 @@ class Problem2D:
     """u_t + f(u)_x + g(u)_y = 0 on a rectangle (Eq. 2DHCL); advection
     f = a u, g = b u; Burgers f = g = u^2/2; Euler (rho, rho u, rho v, rho e),
     limited in the characteristic fields of the rotated decomposition
-    (Section 4).  Periodic: Nx x Ny cells on both meshes.  Transmissive: the
-    mesh of parity 0 has the (Nx+1) x (Ny+1) cells centred at the mesh points
-    (edges included), parity 1 the Nx x Ny cells between them (Section 3.1);
-    ghosts copy the adjacent cell."""
+    (Section 4).  `bc` names the edges of both directions, or is a pair
+    (x, y).  Periodic: N cells on both meshes in that direction.
+    Transmissive: the mesh of parity 0 has the N+1 cells centred at the mesh
+    points (edges included), parity 1 the N cells between them (Section
+    3.1); ghosts copy the adjacent cell."""
     equation: str
     P: int
     Nx: int
@@ -368,7 +371,7 @@ class Problem2D:
     b: float = 1.0
     gamma: float = 1.4
     eps: float = 1e-40
-    bc: str = "periodic"
+    bc: object = "periodic"     # "periodic", "transmissive" or a pair (x, y) of them
 
     @property
     def nc(self) -> int:
@@ -378,10 +381,16 @@ class Problem2D:
     def nd(self) -> int:
         return ndof2d(self.P)
 
+    @property
+    def bcs(self) -> tuple:
+        return (self.bc, self.bc) if isinstance(self.bc, str) else tuple(self.bc)
+
     def mesh(self, parity: int) -> tuple:
         """(cells in x, cells in y) of the mesh of this parity."""
-        e = 1 if (self.bc == "transmissive" and parity % 2 == 0) else 0
-        return self.Nx + e, self.Ny + e
+        bx, by = self.bcs
+        ex = 1 if (bx == "transmissive" and parity % 2 == 0) else 0
+        ey = 1 if (by == "transmissive" and parity % 2 == 0) else 0
+        return self.Nx + ex, self.Ny + ey
 
     def mesh_shape(self, parity: int) -> tuple:
         nx, ny = self.mesh(parity)
@@ -405,7 +414,8 @@ class Problem2D:
         s.equation = EQUATIONS[self.equation]
         s.P, s.Nx, s.Ny = self.P, self.Nx, self.Ny
         s.limiter = 1 if self.limiter else 0
-        s.bc = BCS2D[self.bc]
+        s.bc = BCS2D[self.bcs[0]]
+        s.bc_y = BCS2D[self.bcs[1]]
         s.x_left, s.x_right, s.y_left, s.y_right = self.x_left, self.x_right, self.y_left, self.y_right
         s.a, s.b, s.gamma, s.eps = self.a, self.b, self.gamma, self.eps
         return s

@@ -39,7 +39,8 @@
 //
 // Readings (design notes of the repository): state = point value; time step
 // dt = cfl / max_cells(s_x/dx + s_y/dy) from the cell averages, recomputed
-// every half-step and clipped to t_end; periodic or transmissive boundaries.
+// every half-step and clipped to t_end; periodic or transmissive edges, per
+// direction.
 
 #include <cmath>
 #include <cstdint>
@@ -100,7 +101,9 @@ typedef struct {
   int32_t P;         // degree 0..4
   int64_t Nx, Ny;    // mesh intervals per direction
   int32_t limiter;
-  int32_t bc;        // 0 periodic, 1 transmissive (see Mesh below)
+  int32_t bc;        // x edges: 0 periodic, 1 transmissive (see Mesh below)
+  int32_t bc_y;      // y edges: likewise; -1: as bc
+  int32_t pad2;
   double x_left, x_right, y_left, y_right;
   double a, b;       // advection velocity
   double gamma;
@@ -427,31 +430,32 @@ void char_limit2d(int P, double gamma, double eps, double dx, double dy, const d
       for (int l = 0; l <= n; ++l) D[r][n - l][l] = out[r][n - l][l];
 }
 
-// The two meshes of Section 3.1.  Periodic: Nx x Ny cells on both, centred
-// at (x_left + i dx, y_left + j dy) (parity 0) and shifted by (dx/2, dy/2)
-// (parity 1), indices wrapped.  Transmissive: parity 0 is the mesh of the
-// (Nx+1) x (Ny+1) mesh points x_i, y_j (the domain's edges included),
-// parity 1 the Nx x Ny cells between them; a new parity-0 cell on the edge
-// has parents outside the staggered mesh, which are copies (all DOFs) of the
-// adjacent staggered cell -- the 1D transmissive ghost rule applied in each
-// direction, corners included.
+// The two meshes of Section 3.1, direction by direction.  Periodic: Nx cells
+// on both meshes, centred at x_left + i dx (parity 0) and shifted by dx/2
+// (parity 1), indices wrapped.  Transmissive: parity 0 has the Nx+1 cells
+// centred at the mesh points x_i (the domain's edges included), parity 1 the
+// Nx cells between them; a new parity-0 cell on an edge has parents outside
+// the staggered mesh, which are copies (all DOFs) of the adjacent staggered
+// cell -- the 1D transmissive ghost rule, corners included.  Likewise in y.
 struct Mesh {
   int64_t nx, ny;     // cells of this mesh
-  bool periodic;
+  bool periodic_x, periodic_y;
   int64_t mapx(int64_t i) const {
-    if (periodic) return (i % nx + nx) % nx;
+    if (periodic_x) return (i % nx + nx) % nx;
     return i < 0 ? 0 : (i >= nx ? nx - 1 : i);
   }
   int64_t mapy(int64_t j) const {
-    if (periodic) return (j % ny + ny) % ny;
+    if (periodic_y) return (j % ny + ny) % ny;
     return j < 0 ? 0 : (j >= ny ? ny - 1 : j);
   }
 };
 
+inline int bc_y_of(const wcc2d_oracle_problem& pb) { return pb.bc_y < 0 ? pb.bc : pb.bc_y; }
+
 inline Mesh mesh_of(const wcc2d_oracle_problem& pb, int parity) {
-  const bool per = pb.bc == 0;
-  const int64_t e = (per || parity == 1) ? 0 : 1;
-  return Mesh{pb.Nx + e, pb.Ny + e, per};
+  const bool px = pb.bc == 0, py = bc_y_of(pb) == 0;
+  const int64_t ex = (px || parity == 1) ? 0 : 1, ey = (py || parity == 1) ? 0 : 1;
+  return Mesh{pb.Nx + ex, pb.Ny + ey, px, py};
 }
 
 // Wave-speed rate s_x/dx + s_y/dy of a conserved average (1/time units).
@@ -666,7 +670,7 @@ int32_t wcc2d_oracle_old_cell(const wcc2d_oracle_problem* pb, const double* q, d
 
 int32_t wcc2d_oracle_half_step(const wcc2d_oracle_problem* pb, int32_t parity, const double* qin, double dt,
                                double* qout, double* smax, int32_t* flags) {
-  if (!pb || pb->P < 0 || pb->P > w2d::PMAX || pb->Nx < 2 || pb->Ny < 2 || pb->bc < 0 || pb->bc > 1) return -1;
+  if (!pb || pb->P < 0 || pb->P > w2d::PMAX || pb->Nx < 2 || pb->Ny < 2 || pb->bc < 0 || pb->bc > 1 || pb->bc_y < -1 || pb->bc_y > 1) return -1;
   int fl = 0;
   w2d::half_step(*pb, parity, qin, dt, qout, smax, &fl);
   if (flags) *flags = fl;
@@ -680,7 +684,7 @@ int32_t wcc2d_oracle_half_step(const wcc2d_oracle_problem* pb, int32_t parity, c
 // half-steps taken, -1 on bad input.
 int64_t wcc2d_oracle_run(const wcc2d_oracle_problem* pb, int32_t* parity, double* t, double* smax, double* q,
                          double t_end, double cfl, double dt_fixed, int64_t max_half_steps, int32_t* flags) {
-  if (!pb || pb->P < 0 || pb->P > w2d::PMAX || pb->Nx < 2 || pb->Ny < 2 || pb->bc < 0 || pb->bc > 1) return -1;
+  if (!pb || pb->P < 0 || pb->P > w2d::PMAX || pb->Nx < 2 || pb->Ny < 2 || pb->bc < 0 || pb->bc > 1 || pb->bc_y < -1 || pb->bc_y > 1) return -1;
   const size_t per_cell = (size_t)(w2d::ncomp(*pb) * w2d::ndof(pb->P));
   std::vector<double> tmp(per_cell * (size_t)((pb->Nx + 1) * (pb->Ny + 1)));
   int64_t taken = 0;

@@ -53,7 +53,8 @@ class wcc2d_params(ctypes.Structure):
         ("x_left", ctypes.c_double), ("x_right", ctypes.c_double),
         ("y_left", ctypes.c_double), ("y_right", ctypes.c_double),
         ("a", ctypes.c_double), ("b", ctypes.c_double), ("gamma", ctypes.c_double), ("eps", ctypes.c_double),
-        ("limiter", ctypes.c_int32), ("bc", ctypes.c_int32),
+        ("limiter", ctypes.c_int32), ("bc", ctypes.c_int32), ("bc_y", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
     ]
 
 
@@ -350,10 +351,12 @@ class Solver2D:
 
     def __init__(self, equation: str, P: int, Nx: int, Ny: int, *, limiter: bool = True, x_left: float = 0.0,
                  x_right: float = 1.0, y_left: float = 0.0, y_right: float = 1.0, a: float = 1.0, b: float = 1.0,
-                 gamma: float = 1.4, eps: float = 1e-40, bc: str = "periodic", stream=None):
+                 gamma: float = 1.4, eps: float = 1e-40, bc="periodic", stream=None):
         lib = load()
-        if bc not in ("periodic", "transmissive"):
-            raise ValueError(f"2D boundary {bc!r}: periodic or transmissive")
+        bcs = (bc, bc) if isinstance(bc, str) else tuple(bc)
+        if len(bcs) != 2 or any(b not in ("periodic", "transmissive") for b in bcs):
+            raise ValueError(f"2D boundary {bc!r}: periodic or transmissive, or a pair (x, y) of them")
+        self.bcs = bcs
         self.equation, self.P, self.Nx, self.Ny, self.bc = equation, P, Nx, Ny, bc
         self.nc = 4 if equation == "euler" else 1
         self.nd = (P + 1) * (P + 2) // 2
@@ -362,7 +365,7 @@ class Solver2D:
         p.x_left, p.x_right, p.y_left, p.y_right = x_left, x_right, y_left, y_right
         p.a, p.b, p.gamma, p.eps = a, b, gamma, eps
         p.limiter = 1 if limiter else 0
-        p.bc = BCS[bc]
+        p.bc, p.bc_y = BCS[bcs[0]], BCS[bcs[1]]
         self.params = p
         h = ctypes.c_void_p()
         _check(lib.wcc2d_create(EQUATIONS[equation], P, Nx, Ny, ctypes.byref(p), ctypes.byref(h)), "wcc2d_create")
@@ -375,8 +378,9 @@ class Solver2D:
                "wcc2d_bind", h, two_d=True)
 
     def mesh_shape(self, parity: int) -> tuple:
-        e = 1 if (self.bc == "transmissive" and parity % 2 == 0) else 0
-        return (self.nc, self.nd, self.Ny + e, self.Nx + e)
+        ex = 1 if (self.bcs[0] == "transmissive" and parity % 2 == 0) else 0
+        ey = 1 if (self.bcs[1] == "transmissive" and parity % 2 == 0) else 0
+        return (self.nc, self.nd, self.Ny + ey, self.Nx + ex)
 
     @property
     def shape(self):

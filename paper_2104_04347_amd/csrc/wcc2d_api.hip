@@ -36,7 +36,7 @@ inline size_t al256(size_t x) { return (x + 255) & ~size_t(255); }
 struct wcc2d_ctx {
   int eq = 0, P = 0, nc = 1, nd = 1;
   int64_t Nx = 0, Ny = 0, plane = 0;
-  int bc = WCC_BC_PERIODIC;
+  int bc = WCC_BC_PERIODIC, bc_y = WCC_BC_PERIODIC;   // x and y edges
   wcc2d_params prm{};
   char* ws = nullptr;
   size_t ws_bytes = 0;
@@ -83,7 +83,7 @@ double dy_of(const wcc2d_ctx* c) { return (c->prm.y_right - c->prm.y_left) / (do
 // transmissive mesh) or (Nx+1) x (Ny+1) (the transmissive mesh of the mesh
 // points).
 int64_t mesh_nx(const wcc2d_ctx* c, int parity) { return c->Nx + (c->bc == WCC_BC_PERIODIC || parity ? 0 : 1); }
-int64_t mesh_ny(const wcc2d_ctx* c, int parity) { return c->Ny + (c->bc == WCC_BC_PERIODIC || parity ? 0 : 1); }
+int64_t mesh_ny(const wcc2d_ctx* c, int parity) { return c->Ny + (c->bc_y == WCC_BC_PERIODIC || parity ? 0 : 1); }
 
 Step2Args args_for(const wcc2d_ctx* c, int parity, int slot, double dt_fixed) {
   Step2Args a{};
@@ -96,7 +96,8 @@ Step2Args args_for(const wcc2d_ctx* c, int parity, int slot, double dt_fixed) {
   a.nyo = (int32_t)mesh_ny(c, parity);
   a.nxn = (int32_t)mesh_nx(c, 1 - parity);
   a.nyn = (int32_t)mesh_ny(c, 1 - parity);
-  a.periodic = c->bc == WCC_BC_PERIODIC ? 1 : 0;
+  a.periodic_x = c->bc == WCC_BC_PERIODIC ? 1 : 0;
+  a.periodic_y = c->bc_y == WCC_BC_PERIODIC ? 1 : 0;
   a.parity_old = parity;
   a.slot = slot;
   a.dx = dx_of(c);
@@ -240,6 +241,7 @@ int wcc2d_params_default(wcc2d_params* p) {
   p->gamma = 1.4;
   p->eps = 1e-40;
   p->limiter = 1;
+  p->bc_y = -1;
   return WCC_OK;
 }
 
@@ -251,6 +253,7 @@ int wcc2d_create(int equation, int P, int64_t Nx, int64_t Ny, const wcc2d_params
   wcc2d_params prm;
   if (params) prm = *params; else wcc2d_params_default(&prm);
   if (prm.bc != WCC_BC_PERIODIC && prm.bc != WCC_BC_TRANSMISSIVE) return WCC_EINVAL;
+  if (prm.bc_y != -1 && prm.bc_y != WCC_BC_PERIODIC && prm.bc_y != WCC_BC_TRANSMISSIVE) return WCC_EINVAL;
   if (!(prm.x_right > prm.x_left) || !(prm.y_right > prm.y_left) || !(prm.eps >= 0.0)) return WCC_EINVAL;
   if (equation == WCC_EULER && !(prm.gamma > 1.0)) return WCC_EINVAL;
   wcc2d_ctx* c = new wcc2d_ctx();
@@ -261,6 +264,7 @@ int wcc2d_create(int equation, int P, int64_t Nx, int64_t Ny, const wcc2d_params
   c->Nx = Nx;
   c->Ny = Ny;
   c->bc = prm.bc;
+  c->bc_y = prm.bc_y < 0 ? prm.bc : prm.bc_y;
   c->plane = (mesh_nx(c, 0) * mesh_ny(c, 0) + 63) / 64 * 64;
   c->prm = prm;
   int dev = 0;

@@ -17,7 +17,8 @@ struct Step2Args {
   int32_t Nx, Ny;         // mesh intervals (dx = domain width / Nx)
   int32_t nxo, nyo;       // cells of the old mesh (row width nxo)
   int32_t nxn, nyn;       // cells of the new mesh
-  int32_t periodic;       // 1: indices wrap; 0: transmissive, indices clamp to the edge cell
+  int32_t periodic_x;     // 1: indices wrap; 0: transmissive, indices clamp to the edge cell
+  int32_t periodic_y;
   int32_t parity_old;     // 0: original -> staggered mesh, 1: back
   int32_t slot;           // ring slot of this launch
   double dx, dy;

@@ -157,7 +157,7 @@ __device__ __forceinline__ void run_tile2(const Step2Args& a, int tile, int tile
   const int lx = lane & 7, ly = lane >> 3;
   const int off = a.parity_old == 0 ? 0 : -1;
   Old2<EQ, P> o;
-  old_of<EQ, P>(a, map_idx(7 * tx + lx + off, a.nxo, a.periodic), map_idx(7 * ty + ly + off, a.nyo, a.periodic), nlx,
+  old_of<EQ, P>(a, map_idx(7 * tx + lx + off, a.nxo, a.periodic_x), map_idx(7 * ty + ly + off, a.nyo, a.periodic_y), nlx,
                 nly, o);
   const int ni = 7 * tx + lx, nj = 7 * ty + ly;
   const bool mine = lx < 7 && ly < 7 && ni < a.nxn && nj < a.nyn;
@@ -252,15 +252,15 @@ __global__ __launch_bounds__(256) void k2d_half_step_rows(const Step2Args a) {
   double qn[NC][ND];
   if (PF && u_begin < u_end) {
     const int sx = u_begin / rows, r = u_begin - sx * rows;
-    load_old<EQ, P>(a, map_idx(63 * sx + lane + off, a.nxo, a.periodic), map_idx(r + 1 + off, a.nyo, a.periodic), qn);
+    load_old<EQ, P>(a, map_idx(63 * sx + lane + off, a.nxo, a.periodic_x), map_idx(r + 1 + off, a.nyo, a.periodic_y), qn);
   }
   for (int u = u_begin; u < u_end; ++u) {
     const int sx = u / rows, r = u - sx * rows;
-    const int i = map_idx(63 * sx + lane + off, a.nxo, a.periodic);
+    const int i = map_idx(63 * sx + lane + off, a.nxo, a.periodic_x);
     if (u == u_begin || r == 0) {
       // lower parents of new row r: the old row below, expanded afresh
       Old2<EQ, P> o;
-      old_of<EQ, P>(a, i, map_idx(r + off, a.nyo, a.periodic), nlx, nly, o);
+      old_of<EQ, P>(a, i, map_idx(r + off, a.nyo, a.periodic_y), nlx, nly, o);
 #pragma unroll
       for (int c = 0; c < NC; ++c) put_carry<EQ, P>(carry, c, lane, o);
     }
@@ -272,12 +272,12 @@ __global__ __launch_bounds__(256) void k2d_half_step_rows(const Step2Args a) {
         for (int d = 0; d < ND; ++d) q[c][d] = qn[c][d];
       if (u + 1 < u_end) {
         const int sx2 = (u + 1) / rows, r2 = u + 1 - sx2 * rows;
-        load_old<EQ, P>(a, map_idx(63 * sx2 + lane + off, a.nxo, a.periodic), map_idx(r2 + 1 + off, a.nyo, a.periodic),
+        load_old<EQ, P>(a, map_idx(63 * sx2 + lane + off, a.nxo, a.periodic_x), map_idx(r2 + 1 + off, a.nyo, a.periodic_y),
                         qn);
       }
       __builtin_amdgcn_sched_barrier(0);
     } else {
-      load_old<EQ, P>(a, i, map_idx(r + 1 + off, a.nyo, a.periodic), q);
+      load_old<EQ, P>(a, i, map_idx(r + 1 + off, a.nyo, a.periodic_y), q);
     }
     Old2<EQ, P> o;
     old_cell2<EQ, P>(q, nlx, nly, a.ph, o);

@@ -373,14 +373,15 @@ def dof_pairs(P: int):
     return [(n - l, l) for n in range(P + 1) for l in range(n + 1)]
 
 
-def centers2d(x_left, x_right, y_left, y_right, Nx, Ny, parity, bc: str = "periodic"):
-    """Cell centres (X, Y) of the mesh of this parity (Section 3.1): periodic,
-    Nx x Ny cells on both meshes, the staggered one shifted by (dx/2, dy/2);
-    transmissive, the (Nx+1) x (Ny+1) mesh points on parity 0 (edges
-    included) and the Nx x Ny cells between them on parity 1.  Arrays of
-    shape (rows, columns)."""
-    x = centers(x_left, x_right, Nx, n_cells(Nx, bc, parity), parity)
-    y = centers(y_left, y_right, Ny, n_cells(Ny, bc, parity), parity)
+def centers2d(x_left, x_right, y_left, y_right, Nx, Ny, parity, bc="periodic"):
+    """Cell centres (X, Y) of the mesh of this parity (Section 3.1), per
+    direction (`bc` a name or a pair (x, y) of names): periodic, N cells on
+    both meshes, the staggered one shifted by half a cell; transmissive, the
+    N+1 mesh points on parity 0 (edges included) and the N cells between them
+    on parity 1.  Arrays of shape (rows, columns)."""
+    bx, by = (bc, bc) if isinstance(bc, str) else bc
+    x = centers(x_left, x_right, Nx, n_cells(Nx, bx, parity), parity)
+    y = centers(y_left, y_right, Ny, n_cells(Ny, by, parity), parity)
     return np.meshgrid(x, y)
 
 
@@ -506,5 +507,38 @@ def riemann2d(config: int, P: int, N: int, parity: int = 0, gamma: float = 1.4):
         cons = (rho, rho * u, rho * v, p / (gamma - 1.0) + 0.5 * rho * (u * u + v * v))
         for c in range(4):
             q[c, 0] += w * cons[c]
+    return q
+
+
+def richtmyer_meshkov(P: int, Nx: int, Ny: int, parity: int = 0, gamma: float = 1.4, mach: float = 2.0,
+                      quad: int = 8):
+    """Single-mode Richtmyer-Meshkov set-up of Section 5.3 on [-0.5, 0.5] x
+    [0, 5], periodic in x, transmissive in y: light gas (0.1, 0, 0, 1/gamma)
+    above y = 1 - 0.3 cos(2 pi x), heavy gas (1, 0, 0, 1/gamma) below it down
+    to y = 0.6, and below that the post-shock state of a Mach `mach` shock
+    moving up into the heavy gas (normal-shock relations, as the paper writes
+    them).  Each cell holds the mean of the conserved variables over the cell
+    (a quad x quad Gauss-Legendre rule on each cell; the interfaces make the
+    data piecewise constant) as its point value, derivatives zero."""
+    r2, p2 = 1.0, 1.0 / gamma
+    a2 = np.sqrt(gamma * p2 / r2)
+    m2 = mach * mach
+    rs = r2 * 0.5 * (gamma + 1.0) * m2 / (1.0 + 0.5 * (gamma - 1.0) * m2)
+    vs = a2 * 2.0 * (m2 - 1.0) / ((gamma + 1.0) * mach)
+    ps = p2 * (2.0 * gamma * m2 - gamma + 1.0) / (gamma + 1.0)
+    states = {1: (0.1, 0.0, 0.0, 1.0 / gamma), 2: (r2, 0.0, 0.0, p2), 3: (rs, 0.0, vs, ps)}
+    hx, hy = 1.0 / Nx, 5.0 / Ny
+    X, Y = centers2d(-0.5, 0.5, 0.0, 5.0, Nx, Ny, parity, ("periodic", "transmissive"))
+    g, w = np.polynomial.legendre.leggauss(quad)
+    q = np.zeros((4, ndof2d(P)) + X.shape)
+    for gi, wi in zip(g, w):
+        for gj, wj in zip(g, w):
+            xs, ys = X + 0.5 * hx * gi, Y + 0.5 * hy * gj
+            region = np.where(ys >= 1.0 - 0.3 * np.cos(2 * np.pi * xs), 1, np.where(ys >= 0.6, 2, 3))
+            for k, (rho, u, v, p) in states.items():
+                cons = (rho, rho * u, rho * v, p / (gamma - 1.0) + 0.5 * rho * (u * u + v * v))
+                m = (region == k) * (0.25 * wi * wj)
+                for c in range(4):
+                    q[c, 0] += m * cons[c]
     return q
 

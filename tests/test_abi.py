@@ -101,7 +101,7 @@ def test_2d_create_validates():
     h = ctypes.c_void_p()
     p = binding.wcc2d_params()
     assert lib.wcc2d_params_default(ctypes.byref(p)) == 0
-    assert p.limiter == 1 and p.eps == 1e-40 and p.x_right == 1.0 and p.b == 1.0
+    assert p.limiter == 1 and p.eps == 1e-40 and p.x_right == 1.0 and p.b == 1.0 and p.bc == 0 and p.bc_y == -1
     for eq, P, nx, ny in [(3, 2, 64, 64), (0, 4, 64, 64), (0, -1, 64, 64), (0, 2, 1, 64), (0, 2, 1 << 15, 1 << 14)]:
         assert lib.wcc2d_create(eq, P, nx, ny, ctypes.byref(p), ctypes.byref(h)) == binding.WCC_EINVAL
     p.bc = 2                                   # Dirichlet is a 1D boundary only
@@ -112,7 +112,12 @@ def test_2d_create_validates():
     assert lib.wcc2d_workspace_bytes(h, ctypes.byref(nb_t)) == 0
     assert nb_t.value >= 2 * 6 * (65 * 65) * 8             # planes sized for the (Nx+1) x (Ny+1) mesh
     lib.wcc2d_destroy(h)
-    p.bc = 0
+    p.bc, p.bc_y = 0, 2                        # per-direction edges: periodic or transmissive only
+    assert lib.wcc2d_create(1, 2, 64, 64, ctypes.byref(p), ctypes.byref(h)) == binding.WCC_EINVAL
+    p.bc_y = 1
+    assert lib.wcc2d_create(1, 2, 64, 64, ctypes.byref(p), ctypes.byref(h)) == 0
+    lib.wcc2d_destroy(h)
+    p.bc, p.bc_y = 0, -1
     # Euler needs gamma > 1; with it, both the limited and the unlimited form exist
     p.gamma = 1.0
     assert lib.wcc2d_create(2, 2, 64, 64, ctypes.byref(p), ctypes.byref(h)) == binding.WCC_EINVAL

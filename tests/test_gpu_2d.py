@@ -163,14 +163,14 @@ def test_euler_modes_limited_bitwise(P, variant):
     assert_bitwise(q, info, r, f"limited modes P={P}")
 
 
-def oracle_run_t(eq, P, Nx, Ny, q0, dom, parity=0, **kw):
-    pb = oracle.Problem2D(eq, P, Nx, Ny, limiter=True, bc="transmissive", x_left=dom[0], x_right=dom[1],
+def oracle_run_t(eq, P, Nx, Ny, q0, dom, parity=0, bc="transmissive", **kw):
+    pb = oracle.Problem2D(eq, P, Nx, Ny, limiter=True, bc=bc, x_left=dom[0], x_right=dom[1],
                           y_left=dom[2], y_right=dom[3], a=0.7, b=-0.4)
     return oracle.run2d(pb, q0, parity=parity, **kw)
 
 
-def gpu_run_t(eq, P, Nx, Ny, q0, dom, variant, parity=0, half_steps=None, t_end=None, cfl=None):
-    s = binding.Solver2D(eq, P, Nx, Ny, limiter=True, bc="transmissive", x_left=dom[0], x_right=dom[1],
+def gpu_run_t(eq, P, Nx, Ny, q0, dom, variant, parity=0, half_steps=None, t_end=None, cfl=None, bc="transmissive"):
+    s = binding.Solver2D(eq, P, Nx, Ny, limiter=True, bc=bc, x_left=dom[0], x_right=dom[1],
                          y_left=dom[2], y_right=dom[3], a=0.7, b=-0.4)
     try:
         s.set_launch(0, 0, variant)
@@ -218,6 +218,39 @@ def test_riemann2d_bitwise(config, P, variant):
     r = oracle_run_t("euler", P, N, N, q0, dom, t_end=0.1, cfl=CFL[P])
     assert info.t == 0.1
     assert_bitwise(q, info, r, f"Riemann {config} P={P} variant={variant}")
+
+
+@pytest.mark.parametrize("variant", VARIANTS)
+@pytest.mark.parametrize("bc", [("periodic", "transmissive"), ("transmissive", "periodic")])
+@pytest.mark.parametrize("P", [2, 3])
+def test_mixed_edges_bitwise(bc, P, variant):
+    """Edges chosen per direction: (Nx or Nx+1) x (Ny or Ny+1) cells on the
+    parity-0 mesh, 70 x 23 intervals, 11 half-steps."""
+    Nx, Ny = 70, 23
+    dom = (0.0, 2.0, 0.0, 2.0)
+    fn = inputs.modes2d(6)
+    X, Y = inputs.centers2d(*dom, Nx, Ny, 0, bc)
+    q0 = np.zeros((1, inputs.ndof2d(P)) + X.shape)
+    for k, l in inputs.dof_pairs(P):
+        q0[0, inputs.dof2d(k, l)] = (2.0 / Nx) ** k * (2.0 / Ny) ** l * fn.deriv(X, Y, k, l)
+    q, info = gpu_run_t("burgers", P, Nx, Ny, q0, dom, variant, half_steps=11, cfl=CFL[P], bc=bc)
+    r = oracle_run_t("burgers", P, Nx, Ny, q0, dom, bc=bc, cfl=CFL[P], max_half_steps=11)
+    assert q.shape == r.q.shape
+    assert_bitwise(q, info, r, f"mixed {bc} P={P} variant={variant}")
+
+
+@pytest.mark.parametrize("variant", VARIANTS)
+@pytest.mark.parametrize("P", [1, 2, 3])
+def test_richtmyer_meshkov_bitwise(P, variant):
+    """The Richtmyer-Meshkov set-up of Section 5.3 (periodic in x,
+    transmissive in y), limited Euler on 16 x 80 intervals, 24 half-steps."""
+    Nx, Ny = 16, 80
+    dom = (-0.5, 0.5, 0.0, 5.0)
+    bc = ("periodic", "transmissive")
+    q0 = inputs.richtmyer_meshkov(P, Nx, Ny)
+    q, info = gpu_run_t("euler", P, Nx, Ny, q0, dom, variant, half_steps=24, cfl=CFL[P], bc=bc)
+    r = oracle_run_t("euler", P, Nx, Ny, q0, dom, bc=bc, cfl=CFL[P], max_half_steps=24)
+    assert_bitwise(q, info, r, f"Richtmyer-Meshkov P={P} variant={variant}")
 
 
 def test_2d_errors():

@@ -42,8 +42,9 @@ MUTANTS = {
     "right eigenvector energy entry": ("{1.0, u, vv, 0.5 * q2}", "{1.0, u, vv, q2}"),
     "tangential velocity sign": ("ut = std::fma(vv, nx, -(u * ny))", "ut = std::fma(vv, nx, u * ny)"),
     "transmissive ghost wraps in x": ("    return i < 0 ? 0 : (i >= nx ? nx - 1 : i);", "    return (i % nx + nx) % nx;"),
-    "transmissive edge mesh missing": ("const int64_t e = (per || parity == 1) ? 0 : 1;",
-                                       "const int64_t e = (per || parity == 0) ? 0 : 1;"),
+    "transmissive edge mesh missing": ("ex = (px || parity == 1) ? 0 : 1", "ex = (px || parity == 0) ? 0 : 1"),
+    "y edges follow x": ("const bool px = pb.bc == 0, py = bc_y_of(pb) == 0;",
+                         "const bool px = pb.bc == 0, py = px;"),
 }
 
 
@@ -66,6 +67,7 @@ def quick_pins() -> list:
         ("Burgers diagonal", lambda: t2.test_burgers_diagonal_order(2)),
         ("transmissive 1D Euler", lambda: t2t.test_reduces_to_1d_euler_transmissive(2)),
         ("transmissive interior", lambda: t2t.test_interior_equals_periodic("burgers", 3)),
+        ("mixed edges 1D", lambda: t2t.test_periodic_x_transmissive_y_reduces_to_1d(2)),
     ]
     failed = []
     for name, fn in checks:
