@@ -118,6 +118,12 @@ int wcc2d_advance(wcc2d_ctx* c, double t_end, double cfl, int64_t max_half_steps
  * and fill info (if non-null); synchronises the stream. */
 int wcc2d_read_dofs(wcc2d_ctx* c, double* host, int64_t cap, wcc2d_state_info* info);
 
+/* Conserved totals sum over the current mesh of ubar dx dy per component
+ * (cell averages of the cell polynomials), summed in cell order on the host.
+ * Synchronous.  With periodic edges they are invariants of the scheme up to
+ * round-off.  Errors: WCC_EINVAL, WCC_ESTATE (no state). */
+int wcc2d_totals(wcc2d_ctx* c, double* per_component);
+
 /* Launch shape: threads per block (64..256, multiple of 64; 0 = 256),
  * blocks per launch (0 = resident capacity) and the work decomposition
  * (variant 0: every wavefront expands 8 x 8 old-cell tiles and produces their

@@ -106,6 +106,7 @@ SIGNATURES = {
     "wcc2d_advance": ([_vp, _c.c_double, _c.c_double, _i64, _c.POINTER(_i64)], _c.c_int),
     "wcc2d_read_dofs": ([_vp, _dp, _i64, _c.POINTER(wcc2d_state_info)], _c.c_int),
     "wcc2d_set_launch": ([_vp, _c.c_int, _c.c_int, _c.c_int], _c.c_int),
+    "wcc2d_totals": ([_vp, _dp], _c.c_int),
     "wcc2d_last_run_ms": ([_vp, _dp], _c.c_int),
     "wcc2d_last_error": ([_vp], _c.c_char_p),
     "wcc2d_destroy": ([_vp], None),
@@ -415,6 +416,12 @@ class Solver2D:
         _check(load().wcc2d_read_dofs(self.h, _dptr(q), q.size, ctypes.byref(inf)), "wcc2d_read_dofs", self.h,
                two_d=True)
         return q, inf
+
+    def totals(self) -> np.ndarray:
+        """Sum of the cell averages times dx dy per component (host sum)."""
+        out = np.zeros(self.nc)
+        _check(load().wcc2d_totals(self.h, _dptr(out)), "wcc2d_totals", self.h, two_d=True)
+        return out
 
     def set_launch(self, threads: int = 0, blocks: int = 0, variant: int = -1) -> None:
         _check(load().wcc2d_set_launch(self.h, int(threads), int(blocks), int(variant)), "wcc2d_set_launch", self.h,

@@ -430,6 +430,40 @@ int wcc2d_read_dofs(wcc2d_ctx* c, double* host, int64_t cap, wcc2d_state_info* i
   return WCC_OK;
 }
 
+int wcc2d_totals(wcc2d_ctx* c, double* per_component) {
+  if (!c || !per_component) return WCC_EINVAL;
+  wcc2d_state_info info;
+  const size_t cap = (size_t)c->nc * c->nd * (size_t)(mesh_nx(c, 0) * mesh_ny(c, 0));
+  std::vector<double> buf(cap);
+  const int rc = wcc2d_read_dofs(c, buf.data(), (int64_t)cap, &info);
+  if (rc) return rc;
+  const int64_t cells = info.Nx * info.Ny;
+  const int P = c->P, nd = c->nd;
+  // cell average of the cell polynomial: the point value plus the even-even
+  // moments, 1/((k+1)! 2^k (l+1)! 2^l) u_{kx,ly} (the quarter averages summed)
+  std::vector<double> w(nd, 0.0);
+  for (int n = 2; n <= P; ++n)
+    for (int l = 0; l <= n; ++l) {
+      const int k = n - l;
+      if (k % 2 || l % 2) continue;
+      double f = 1.0;
+      for (int i = 2; i <= k + 1; ++i) f *= i;
+      for (int i = 2; i <= l + 1; ++i) f *= i;
+      w[(n * (n + 1)) / 2 + l] = 1.0 / (f * std::ldexp(1.0, k + l));
+    }
+  for (int cc = 0; cc < c->nc; ++cc) {
+    double tot = 0.0;
+    for (int64_t j = 0; j < cells; ++j) {
+      double a = buf[(size_t)(cc * nd) * cells + j];
+      for (int d = 1; d < nd; ++d)
+        if (w[d] != 0.0) a += w[d] * buf[(size_t)(cc * nd + d) * cells + j];
+      tot += a;
+    }
+    per_component[cc] = tot * info.dx * info.dy;
+  }
+  return WCC_OK;
+}
+
 int wcc2d_set_launch(wcc2d_ctx* c, int threads_per_block, int blocks, int variant) {
   if (!c) return WCC_EINVAL;
   if (variant < -1 || variant > 2) return fail2(c, WCC_EINVAL, "variant must be -1 (keep), 0, 1 or 2");

@@ -253,6 +253,47 @@ def test_richtmyer_meshkov_bitwise(P, variant):
     assert_bitwise(q, info, r, f"Richtmyer-Meshkov P={P} variant={variant}")
 
 
+@pytest.mark.parametrize("eq", ["burgers", "euler"])
+def test_totals_conserved_periodic(eq):
+    """Periodic edges: the cell-average totals are invariants of the scheme;
+    after 60 limited half-steps they move only by the round-off of their
+    own host sums (about sqrt(cells) u64 sum|ubar|, a factor 8 allowed)."""
+    P, N = 3, 64
+    if eq == "euler":
+        q0 = inputs.isentropic_vortex(P, N)
+        dom = (-5.0, 5.0, -5.0, 5.0)
+    else:
+        q0 = modes_state(P, N, N, seed=9)
+        dom = (0.0, 2.0, 0.0, 2.0)
+    s = binding.Solver2D(eq, P, N, N, limiter=True, x_left=dom[0], x_right=dom[1], y_left=dom[2], y_right=dom[3])
+    try:
+        s.write(q0)
+        tot0 = s.totals()
+        s.run(60, CFL[P])
+        tot = s.totals()
+        q, info = s.read()
+    finally:
+        s.close()
+    assert info.flags & 3 == 0 and info.half_steps == 60
+    abs_sum = np.abs(q[:, 0]).sum(axis=(1, 2)) * info.dx * info.dy
+    bound = 8 * N * 2.0 ** -53 * abs_sum
+    assert np.all(np.abs(tot - tot0) <= bound), (tot - tot0, bound)
+    # the totals are those of the state: mean of the cell polynomials
+    area = (dom[1] - dom[0]) * (dom[3] - dom[2])
+    assert np.allclose(tot0 / area, [np.mean(averages_of(P, q0[c])) for c in range(q0.shape[0])], rtol=1e-14)
+
+
+def averages_of(P, qc):
+    """Cell averages of one component's state (Eq. SubEq:2DCellAVG): the
+    point value plus the even-even moments of the cell polynomial."""
+    from math import factorial
+    out = qc[0].copy()
+    for k, l in inputs.dof_pairs(P):
+        if (k, l) != (0, 0) and k % 2 == 0 and l % 2 == 0:
+            out = out + qc[inputs.dof2d(k, l)] / (factorial(k + 1) * 2 ** k * factorial(l + 1) * 2 ** l)
+    return out
+
+
 def test_2d_errors():
     s = binding.Solver2D("burgers", 2, 16, 16)
     with pytest.raises(binding.WccError):
