@@ -76,7 +76,7 @@ def bytes_per_launch(N: int, P: int, nc: int, precision: str) -> float:
     return float(n_old_plus_new * b_cell)
 
 
-def launch_shape_single(args, s, q0) -> dict:
+def launch_shape_single(args, s, q0, cfl=None, **tune_kw) -> dict:
     """Launch shape of the single-instance kernel: a cached autotuner result
     when there is one (and --tune is not 'force'), else tune now (--tune off:
     the library's default).  Results do not depend on the shape."""
@@ -87,8 +87,9 @@ def launch_shape_single(args, s, q0) -> dict:
         c = autotune.cached_single(s)
         return {"threads": c["threads"], "blocks": c["blocks"], "variant": c.get("variant", 0),
                 "source": "autotune cache"}
-    best = autotune.tune_single(s, q0, args.cfl)
-    return {"threads": best["threads"], "blocks": best["blocks"], "variant": best["variant"], "source": "autotuned"}
+    best = autotune.tune_single(s, q0, args.cfl if cfl is None else cfl, **tune_kw)
+    return {"threads": best["threads"], "blocks": best["blocks"], "variant": best["variant"], "source": "autotuned",
+            "best_us_per_variant": {str(v): round(ms * 1e3, 2) for v, ms in best["per_variant_ms"].items()}}
 
 
 def time_single(args, precision: str, q0):
@@ -274,6 +275,8 @@ def time_large(args):
     finals = {}
     for prec in ("fp32_mixed", "fp64"):
         s = binding.Solver("euler", P, N, "periodic", limiter=True, precision=prec)
+        # kernel variant only (a short tune: each candidate costs ~1 ms per half-step)
+        shape = launch_shape_single(args, s, q0, cfl, steps=96, threads=(256,), block_factors=(0,))
         s.write(q0)
         tot0 = s.totals()
         torch.cuda.synchronize()
@@ -287,6 +290,7 @@ def time_large(args):
         abs0 = np.abs(q0[:, 0]).sum(axis=1) * (1.0 / N)   # scale of the totals
         out[prec] = {"value": N * 3 * (P + 1) * args.large_steps / wall, "unit": "cell-DOF updates/s",
                      "wall_s": wall, "ms_per_step": s.last_run_ms() / args.large_steps, "t": info.t,
+                     "launch": shape,
                      "flags": int(info.flags),
                      "drift_rel": [float(abs(a - b) / c) for a, b, c in zip(tot, tot0, abs0)]}
         del q
@@ -442,6 +446,8 @@ def main():
                     tflops=flops / 1e12, alu_frac=flops / peak_alu, alu_peak=peak_alu)
 
     ro = roof(r64, "fp64")
+    # the counter record is per kernel variant (prefetch / staged stores)
+    kernel_key = f"k_half_step<euler,P={args.P},limiter,f64,variant={r64['launch']['variant']}>"
     bound_hbm = ro["hbm_frac"] >= ro["alu_frac"]
     roofline = {
         "bound": "hbm" if bound_hbm else "alu",
@@ -449,8 +455,8 @@ def main():
         "peak": HBM_PEAK / 1e9 if bound_hbm else FP64_VALU_PEAK / 1e12,
         "unit": "GB/s" if bound_hbm else "TFLOP/s",
         "frac": round(ro["hbm_frac"] if bound_hbm else ro["alu_frac"], 4),
-        "traffic": measured_traffic(f"k_half_step<euler,P={args.P},limiter,f64>", args.N),
-        "kernel": f"k_half_step<euler,P={args.P},limiter,f64>",
+        "traffic": measured_traffic(kernel_key, args.N),
+        "kernel": kernel_key,
         "launch_us": round(ro["launch_us"], 2),
         "bytes_per_launch": ro["bytes_per_launch"],
         "other_roof": ({"bound": "alu", "achieved": round(ro["tflops"], 3), "unit": "TFLOP/s",

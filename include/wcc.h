@@ -149,9 +149,12 @@ int wcc_totals(wcc_ctx* ctx, double* per_component);
 
 /* Launch shape of the half-step kernel: threads per block (64, 128, 192 or
  * 256; 0 = 256), blocks (0 = enough to fill the device at the kernel's
- * occupancy) and kernel variant (0: load a tile, then compute it; 1: load the
- * next tile's inputs while computing the current one (default); -1 keeps the
- * current variant).  Used by the autotuner; results do not depend on it. */
+ * occupancy) and kernel variant, a sum of bits: 1 = load the next tile's
+ * inputs while computing the current one; 2 = store the new cells in whole
+ * 64-cell groups staged through LDS instead of one 63-cell tile per wave
+ * (pays when the state does not fit the caches).  0 (the default) is
+ * neither; -1 keeps the current variant; values outside -1..3 return
+ * WCC_EINVAL.  Used by the autotuner; results do not depend on it. */
 int wcc_set_launch(wcc_ctx* ctx, int threads_per_block, int blocks, int variant);
 
 /* Number of kernel launches and the device time of the last wcc_run call
@@ -186,7 +189,9 @@ int wcc_batch_read_dofs(wcc_batch* bt, int b, double* host, int64_t cap, wcc_sta
  * current value), blocks per launch (0 = fill the device at the kernel's
  * occupancy) and mode (0 keeps the current one; 1 = fused: one launch per
  * half-step over all tiles, degree switched per tile; 2 = grouped: one launch
- * per degree per half-step).  Results do not depend on the schedule. */
+ * per degree per half-step (the default); 3 and 4 = fused and grouped with
+ * the new cells staged in LDS and stored in whole 64-cell groups; other
+ * values return WCC_EINVAL).  Results do not depend on the schedule. */
 int wcc_batch_set_schedule(wcc_batch* bt, int threads_per_block, int blocks, int mode);
 int wcc_batch_last_run_ms(wcc_batch* bt, double* ms);
 const char* wcc_batch_last_error(const wcc_batch* bt);

@@ -4,10 +4,12 @@ Results never depend on the launch shape (every tile runs the same per-cell
 arithmetic; the batched kernels are checked bit for bit against
 single-instance runs in both schedules), so the tuner only measures time:
 
-* single instance: threads per block (64..256) x blocks per launch
+* single instance: kernel variant (prefetch, staged line-aligned stores,
+  both, neither) x threads per block (64..256) x blocks per launch
   (multiples of the device's resident-block capacity);
 * batched: schedule mode (fused: one launch per half-step switching on the
-  degree per tile; grouped: one launch per degree) x threads x blocks.
+  degree per tile; grouped: one launch per degree; each with or without
+  staged stores) x threads x blocks.
 
 Each candidate is timed with HIP events around graph-replayed half-steps on
 the caller's stream, after a warm-up; the best shape is cached in a JSON file
@@ -56,7 +58,7 @@ def key_single(equation: str, P: int, N: int, precision: str, limiter: bool) -> 
 
 
 def tune_single(solver: "binding.Solver", q0: np.ndarray, cfl: float, steps: int = 480,
-                threads=(128, 256), block_factors=(0, 2, 3, 4, 5, 6, 8), variants=(0, 1),
+                threads=(128, 256), block_factors=(0, 2, 3, 4, 5, 6, 8), variants=(0, 1, 2, 3),
                 verbose: bool = False) -> dict:
     """Time the candidate shapes on `solver` (state q0, CFL cfl); keep the best.
     Blocks per launch = block factor x compute units; factor 0 = the
@@ -88,6 +90,7 @@ def tune_single(solver: "binding.Solver", q0: np.ndarray, cfl: float, steps: int
     if default_ms <= best["ms_per_step"]:
         best = {"variant": 0, "threads": 0, "blocks": 0, "ms_per_step": default_ms}
     best["default_ms_per_step"] = default_ms
+    best["per_variant_ms"] = {v: min(r["ms_per_step"] for r in results if r["variant"] == v) for v in variants}
     best["tried"] = results
     c = _load_cache()
     c[key_single(solver.equation, solver.P, solver.N, binding.PRECISIONS_NAME[solver.params.precision],
@@ -124,7 +127,7 @@ def apply_single(solver: "binding.Solver") -> bool:
     return True
 
 
-def tune_batch(batch: "binding.Batch", cfl_by_P, steps: int = 24, modes=(1, 2),
+def tune_batch(batch: "binding.Batch", cfl_by_P, steps: int = 24, modes=(1, 2, 3, 4),
                threads=(128, 256), block_factors=(0, 1, 2, 4), verbose: bool = False) -> dict:
     """Time batched schedules on a batch whose instances are written and
     prepared.  Candidates run consecutively from the evolving state (the cost

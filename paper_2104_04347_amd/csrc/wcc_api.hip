@@ -57,7 +57,7 @@ struct wcc_ctx {
   int64_t launched = 0;     // kernels enqueued since the write (slot = launched % 3)
   int64_t steps = 0;        // half-steps known to be done (exact after a sync)
   int threads = 256, blocks = 0;
-  int prefetch = 0;          // kernel variant: 1 = prefetch the next tile's inputs
+  int prefetch = 0;          // kernel variant bits: 1 = prefetch the next tile's inputs, 2 = aligned stores
   int cu = 0;
   hipStream_t capture = nullptr;
   hipGraphExec_t graphs[6] = {};
@@ -567,7 +567,7 @@ int wcc_totals(wcc_ctx* c, double* per_component) {
 
 int wcc_set_launch(wcc_ctx* c, int threads_per_block, int blocks, int variant) {
   if (!c) return WCC_EINVAL;
-  if (variant < -1 || variant > 1) return fail(c, WCC_EINVAL, "variant must be -1 (keep), 0 or 1");
+  if (variant < -1 || variant > 3) return fail(c, WCC_EINVAL, "variant must be -1 (keep) or 0..3");
   if (variant >= 0) c->prefetch = variant;
   if (threads_per_block != 0 && (threads_per_block % 64 != 0 || threads_per_block < 64 || threads_per_block > 256))
     return fail(c, WCC_EINVAL, "threads per block must be 64, 128, 192 or 256");

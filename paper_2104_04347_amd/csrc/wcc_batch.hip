@@ -12,7 +12,10 @@
 //             (each launch runs at its own occupancy).
 // Blocks own contiguous, cost-balanced ranges of the tile table; a wave walks
 // its block's range with stride = waves per block, merging consecutive tiles
-// of one instance into one wave-level speed reduction and one atomic.
+// of one instance into one wave-level speed reduction and one atomic.  Either
+// schedule can stage the new cells in LDS and store them in whole 64-cell
+// groups (runs of consecutive tiles of one instance), which keeps partial
+// cache-line stores off HBM when the batch does not fit the caches.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -45,12 +48,9 @@ __device__ __forceinline__ void publish_wave(Ctrl* ctrl, int slot, double smax, 
   }
 }
 
-template <int EQ, int P, bool LIM, class R>
-__device__ __forceinline__ void batch_tile(const BatchArgs<R>& a, const BatchInst& in, int first, int bc,
-                                           Ctrl* ctrl, int lane, double& smax, unsigned& flags) {
-  double dt;
-  const bool go = step_time(ctrl, nullptr, a.slot, in.dx, 0.0, first == 0, dt);
-  if (!go) return;
+// The single-instance view of instance `in` for this launch.
+template <class R>
+__device__ __forceinline__ StepArgs<R> instance_args(const BatchArgs<R>& a, const BatchInst& in, int bc, Ctrl* ctrl) {
   StepArgs<R> s;
   s.p_old = a.p_in + in.p_off;
   s.d_old = a.d_in + in.d_off;
@@ -69,13 +69,48 @@ __device__ __forceinline__ void batch_tile(const BatchArgs<R>& a, const BatchIns
   s.ctrl = ctrl;
   s.parts = nullptr;
   s.slot = a.slot;
+  return s;
+}
+
+template <int EQ, int P, bool LIM, class R>
+__device__ __forceinline__ void batch_tile(const BatchArgs<R>& a, const BatchInst& in, int first, int bc,
+                                           Ctrl* ctrl, int lane, double& smax, unsigned& flags) {
+  double dt;
+  const bool go = step_time(ctrl, nullptr, a.slot, in.dx, 0.0, first == 0, dt);
+  if (!go) return;
+  const StepArgs<R> s = instance_args(a, in, bc, ctrl);
   const double lam = dt / in.dx;
   if ((int64_t)first * 63 < s.n_new) run_tile<EQ, P, LIM, R>(s, first, lam, (R)(-lam), lane, smax, flags);
 }
 
+// Staged form: the tile's new cells go to the wave's LDS region; [lo, hi)
+// returns the cells staged (empty when the instance is finished or the tile
+// lies beyond this mesh's last cell).
+template <int EQ, int P, bool LIM, class R, class S>
+__device__ __forceinline__ void batch_tile_staged(const BatchArgs<R>& a, const BatchInst& in, int first, int bc,
+                                                  Ctrl* ctrl, int lane, int wave, S& st, double& smax,
+                                                  unsigned& flags, int& lo, int& hi) {
+  constexpr int NC = ncomp<EQ>();
+  double dt;
+  const bool go = step_time(ctrl, nullptr, a.slot, in.dx, 0.0, first == 0, dt);
+  if (!go) return;
+  const StepArgs<R> s = instance_args(a, in, bc, ctrl);
+  const double lam = dt / in.dx;
+  if ((int64_t)first * 63 >= s.n_new) return;
+  TileIn<EQ, P, R> ti;
+  fetch_tile<EQ, P, R>(s, first, lane, ti);
+  double pn[NC];
+  R dn[NC][P + 1];
+  if (tile_cells<EQ, P, LIM, R>(s, first, ti, lam, (R)(-lam), lane, smax, flags, pn, dn))
+    stage_put<EQ, P, R>(st, wave * 64 + lane, pn, dn);
+  lo = first * 63;
+  hi = lo + 63 < (int)s.n_new ? lo + 63 : (int)s.n_new;
+}
+
 // P < 0: fused schedule (switch on the instance's degree); P >= 0: the
-// grouped schedule's launch for that degree.
-template <int EQ, int PSEL, bool LIM, class R>
+// grouped schedule's launch for that degree.  STG: staged, line-aligned
+// stores (the block's waves advance in lockstep, two barriers per iteration).
+template <int EQ, int PSEL, bool LIM, class R, bool STG>
 __global__ __launch_bounds__(256) void k_batch_step(const BatchArgs<R> a, const int64_t* __restrict__ block_start,
                                                     int bc) {
   // the wave index is the same in every lane: say so, so that tile and
@@ -86,68 +121,147 @@ __global__ __launch_bounds__(256) void k_batch_step(const BatchArgs<R> a, const 
   int cur = -1;
   double smax = 0.0;
   unsigned flags = 0u;
-  for (int64_t w = t0 + wave; w < t1; w += nw) {
-    const BatchTile tl = a.tiles[w];
-    if (tl.inst != cur) {
-      if (cur >= 0) publish_wave(a.ctrl + cur, a.slot, smax, flags);
-      cur = tl.inst;
-      smax = 0.0;
-      flags = 0u;
-    }
-    const BatchInst in = a.inst[tl.inst];
-    Ctrl* ctrl = a.ctrl + tl.inst;
-    if constexpr (PSEL >= 0) {
-      batch_tile<EQ, PSEL, LIM, R>(a, in, tl.first, bc, ctrl, lane, smax, flags);
-    } else {
-      switch (in.P) {
-        case 0: batch_tile<EQ, 0, false, R>(a, in, tl.first, bc, ctrl, lane, smax, flags); break;
-        case 1: batch_tile<EQ, 1, LIM, R>(a, in, tl.first, bc, ctrl, lane, smax, flags); break;
-        case 2: batch_tile<EQ, 2, LIM, R>(a, in, tl.first, bc, ctrl, lane, smax, flags); break;
-        default: batch_tile<EQ, 3, LIM, R>(a, in, tl.first, bc, ctrl, lane, smax, flags); break;
+  if constexpr (!STG) {
+    for (int64_t w = t0 + wave; w < t1; w += nw) {
+      const BatchTile tl = a.tiles[w];
+      if (tl.inst != cur) {
+        if (cur >= 0) publish_wave(a.ctrl + cur, a.slot, smax, flags);
+        cur = tl.inst;
+        smax = 0.0;
+        flags = 0u;
       }
+      const BatchInst in = a.inst[tl.inst];
+      Ctrl* ctrl = a.ctrl + tl.inst;
+      if constexpr (PSEL >= 0) {
+        batch_tile<EQ, PSEL, LIM, R>(a, in, tl.first, bc, ctrl, lane, smax, flags);
+      } else {
+        switch (in.P) {
+          case 0: batch_tile<EQ, 0, false, R>(a, in, tl.first, bc, ctrl, lane, smax, flags); break;
+          case 1: batch_tile<EQ, 1, LIM, R>(a, in, tl.first, bc, ctrl, lane, smax, flags); break;
+          case 2: batch_tile<EQ, 2, LIM, R>(a, in, tl.first, bc, ctrl, lane, smax, flags); break;
+          default: batch_tile<EQ, 3, LIM, R>(a, in, tl.first, bc, ctrl, lane, smax, flags); break;
+        }
+      }
+    }
+  } else {
+    using S = Stage<EQ, (PSEL >= 0 ? PSEL : kBatchPMax), R>;
+    __shared__ S st;
+    int side = 0;                                   // carry region of this iteration
+    // every wave runs every iteration (the barriers are block-wide)
+    for (int64_t wb = t0; wb < t1; wb += nw) {
+      const int64_t w = wb + wave;
+      int lo = 0, hi = 0, P = 0;
+      BatchTile tl{0, 0};
+      BatchInst in{};
+      if (w < t1) {
+        tl = a.tiles[w];
+        if (tl.inst != cur) {
+          if (cur >= 0) publish_wave(a.ctrl + cur, a.slot, smax, flags);
+          cur = tl.inst;
+          smax = 0.0;
+          flags = 0u;
+        }
+        in = a.inst[tl.inst];
+        Ctrl* ctrl = a.ctrl + tl.inst;
+        P = PSEL >= 0 ? PSEL : in.P;
+        if constexpr (PSEL >= 0) {
+          batch_tile_staged<EQ, PSEL, LIM, R>(a, in, tl.first, bc, ctrl, lane, wave, st, smax, flags, lo, hi);
+        } else {
+          switch (in.P) {
+            case 0:
+              batch_tile_staged<EQ, 0, false, R>(a, in, tl.first, bc, ctrl, lane, wave, st, smax, flags, lo, hi);
+              break;
+            case 1:
+              batch_tile_staged<EQ, 1, LIM, R>(a, in, tl.first, bc, ctrl, lane, wave, st, smax, flags, lo, hi);
+              break;
+            case 2:
+              batch_tile_staged<EQ, 2, LIM, R>(a, in, tl.first, bc, ctrl, lane, wave, st, smax, flags, lo, hi);
+              break;
+            default:
+              batch_tile_staged<EQ, 3, LIM, R>(a, in, tl.first, bc, ctrl, lane, wave, st, smax, flags, lo, hi);
+              break;
+          }
+        }
+      }
+      __syncthreads();
+      if (lo < hi) {
+        // runs: consecutive table entries of one instance with consecutive tiles
+        bool prev = false, next = false;
+        if (w > t0) {
+          const BatchTile tp = a.tiles[w - 1];
+          prev = tp.inst == tl.inst && tp.first == tl.first - 1;
+        }
+        if (w + 1 < t1) {
+          // the next tile continues the run only if it has cells on this mesh
+          const BatchTile tn = a.tiles[w + 1];
+          const int64_t n_new = a.parity_old == 0 ? in.N : (bc == kPeriodic ? in.N : in.N + 1);
+          next = tn.inst == tl.inst && tn.first == tl.first + 1 && (int64_t)tn.first * 63 < n_new;
+        }
+        double* p_new = a.p_out + in.p_off;
+        R* d_new = a.d_out + in.d_off;
+        if constexpr (PSEL >= 0) {
+          stage_flush<EQ, PSEL, R>(st, side, wave, nw, lane, lo, hi, prev, next, p_new, d_new, in.ld);
+        } else {
+          switch (P) {
+            case 0: stage_flush<EQ, 0, R>(st, side, wave, nw, lane, lo, hi, prev, next, p_new, d_new, in.ld); break;
+            case 1: stage_flush<EQ, 1, R>(st, side, wave, nw, lane, lo, hi, prev, next, p_new, d_new, in.ld); break;
+            case 2: stage_flush<EQ, 2, R>(st, side, wave, nw, lane, lo, hi, prev, next, p_new, d_new, in.ld); break;
+            default: stage_flush<EQ, 3, R>(st, side, wave, nw, lane, lo, hi, prev, next, p_new, d_new, in.ld); break;
+          }
+        }
+      }
+      __syncthreads();
+      side ^= 1;
     }
   }
   if (cur >= 0) publish_wave(a.ctrl + cur, a.slot, smax, flags);
 }
 
 template <int EQ, int PSEL, class R>
-static hipError_t launch_b(const BatchArgs<R>& a, const int64_t* bs, int bc, bool lim, int blocks, int threads,
-                           hipStream_t s) {
-  if (lim && PSEL != 0)
-    hipLaunchKernelGGL((k_batch_step<EQ, PSEL, true, R>), dim3(blocks), dim3(threads), 0, s, a, bs, bc);
+static hipError_t launch_b(const BatchArgs<R>& a, const int64_t* bs, int bc, bool lim, bool stg, int blocks,
+                           int threads, hipStream_t s) {
+  const bool l = lim && PSEL != 0;
+  if (l && stg)
+    hipLaunchKernelGGL((k_batch_step<EQ, PSEL, true, R, true>), dim3(blocks), dim3(threads), 0, s, a, bs, bc);
+  else if (l)
+    hipLaunchKernelGGL((k_batch_step<EQ, PSEL, true, R, false>), dim3(blocks), dim3(threads), 0, s, a, bs, bc);
+  else if (stg)
+    hipLaunchKernelGGL((k_batch_step<EQ, PSEL, false, R, true>), dim3(blocks), dim3(threads), 0, s, a, bs, bc);
   else
-    hipLaunchKernelGGL((k_batch_step<EQ, PSEL, false, R>), dim3(blocks), dim3(threads), 0, s, a, bs, bc);
+    hipLaunchKernelGGL((k_batch_step<EQ, PSEL, false, R, false>), dim3(blocks), dim3(threads), 0, s, a, bs, bc);
   return hipGetLastError();
 }
 
 template <int EQ, class R>
-static hipError_t launch_bp(const BatchArgs<R>& a, const int64_t* bs, int bc, int psel, bool lim, int blocks,
-                            int threads, hipStream_t s) {
+static hipError_t launch_bp(const BatchArgs<R>& a, const int64_t* bs, int bc, int psel, bool lim, bool stg,
+                            int blocks, int threads, hipStream_t s) {
   switch (psel) {
-    case -1: return launch_b<EQ, -1, R>(a, bs, bc, lim, blocks, threads, s);
-    case 0: return launch_b<EQ, 0, R>(a, bs, bc, lim, blocks, threads, s);
-    case 1: return launch_b<EQ, 1, R>(a, bs, bc, lim, blocks, threads, s);
-    case 2: return launch_b<EQ, 2, R>(a, bs, bc, lim, blocks, threads, s);
-    case 3: return launch_b<EQ, 3, R>(a, bs, bc, lim, blocks, threads, s);
+    case -1: return launch_b<EQ, -1, R>(a, bs, bc, lim, stg, blocks, threads, s);
+    case 0: return launch_b<EQ, 0, R>(a, bs, bc, lim, stg, blocks, threads, s);
+    case 1: return launch_b<EQ, 1, R>(a, bs, bc, lim, stg, blocks, threads, s);
+    case 2: return launch_b<EQ, 2, R>(a, bs, bc, lim, stg, blocks, threads, s);
+    case 3: return launch_b<EQ, 3, R>(a, bs, bc, lim, stg, blocks, threads, s);
   }
   return hipErrorInvalidValue;
 }
 
 template <class R>
 static hipError_t launch_batch(const BatchArgs<R>& a, const int64_t* bs, int eq, int bc, int psel, bool lim,
-                               int blocks, int threads, hipStream_t s) {
+                               bool stg, int blocks, int threads, hipStream_t s) {
   switch (eq) {
-    case kAdvection: return launch_bp<kAdvection, R>(a, bs, bc, psel, lim, blocks, threads, s);
-    case kBurgers: return launch_bp<kBurgers, R>(a, bs, bc, psel, lim, blocks, threads, s);
-    case kEuler: return launch_bp<kEuler, R>(a, bs, bc, psel, lim, blocks, threads, s);
+    case kAdvection: return launch_bp<kAdvection, R>(a, bs, bc, psel, lim, stg, blocks, threads, s);
+    case kBurgers: return launch_bp<kBurgers, R>(a, bs, bc, psel, lim, stg, blocks, threads, s);
+    case kEuler: return launch_bp<kEuler, R>(a, bs, bc, psel, lim, stg, blocks, threads, s);
   }
   return hipErrorInvalidValue;
 }
 
 template <class R>
-static hipError_t occupancy_batch(int eq, int psel, bool lim, int threads, int* per_cu) {
+static hipError_t occupancy_batch(int eq, int psel, bool lim, bool stg, int threads, int* per_cu) {
   const void* f = nullptr;
-#define WCC_BK(E, PS, L) reinterpret_cast<const void*>(&k_batch_step<E, PS, L, R>)
+#define WCC_BK(E, PS, L)                                                             \
+  (stg ? reinterpret_cast<const void*>(&k_batch_step<E, PS, L, R, true>)             \
+       : reinterpret_cast<const void*>(&k_batch_step<E, PS, L, R, false>))
 #define WCC_BSEL(E)                                                                  \
   switch (psel) {                                                                    \
     case -1: f = lim ? WCC_BK(E, -1, true) : WCC_BK(E, -1, false); break;            \
@@ -187,6 +301,7 @@ struct wcc_batch {
   int64_t p_total = 0, d_total = 0;      // elements per buffer
   // schedule
   bool grouped = true;
+  bool staged = false;                   // line-aligned stores through LDS
   int threads = 256, blocks = 0, cu = 256;
   std::vector<int64_t> block_start;      // fused: blocks+1 entries; grouped: per group blocks+1 entries, concatenated
   std::vector<int> group_blocks;         // grouped: blocks per degree
@@ -275,8 +390,8 @@ void split_range(const wcc_batch* b, int64_t lo, int64_t hi, int nb, std::vector
 int occupancy_for(wcc_batch* b, int psel) {
   int per_cu = 0;
   hipError_t e = b->prm.precision == WCC_FP64
-                     ? wcc::occupancy_batch<double>(b->eq, psel, b->prm.limiter != 0, b->threads, &per_cu)
-                     : wcc::occupancy_batch<float>(b->eq, psel, b->prm.limiter != 0, b->threads, &per_cu);
+                     ? wcc::occupancy_batch<double>(b->eq, psel, b->prm.limiter != 0, b->staged, b->threads, &per_cu)
+                     : wcc::occupancy_batch<float>(b->eq, psel, b->prm.limiter != 0, b->staged, b->threads, &per_cu);
   if (e != hipSuccess || per_cu < 1) per_cu = 1;
   return per_cu;
 }
@@ -351,14 +466,14 @@ int enqueue_batch_step(wcc_batch* b, int parity, int slot, hipStream_t s) {
   const bool lim = b->prm.limiter != 0;
   size_t off = 0;
   if (!b->grouped) {
-    hipError_t e = wcc::launch_batch<R>(a, b->d_bs, b->eq, b->bc, -1, lim, b->group_blocks[0], b->threads, s);
+    hipError_t e = wcc::launch_batch<R>(a, b->d_bs, b->eq, b->bc, -1, lim, b->staged, b->group_blocks[0], b->threads, s);
     if (e != hipSuccess) return bfail(b, WCC_EDEVICE, "batch launch: %s", hipGetErrorString(e));
     return WCC_OK;
   }
   for (int p = 0; p <= wcc::kBatchPMax; ++p) {
     const int nb = b->group_blocks[p];
     if (nb == 0) continue;
-    hipError_t e = wcc::launch_batch<R>(a, b->d_bs + off, b->eq, b->bc, p, lim, nb, b->threads, s);
+    hipError_t e = wcc::launch_batch<R>(a, b->d_bs + off, b->eq, b->bc, p, lim, b->staged, nb, b->threads, s);
     if (e != hipSuccess) return bfail(b, WCC_EDEVICE, "batch launch (P=%d): %s", p, hipGetErrorString(e));
     off += (size_t)nb + 1;
   }
@@ -704,8 +819,11 @@ int wcc_batch_set_schedule(wcc_batch* b, int threads_per_block, int blocks, int 
   if (blocks < 0 || blocks > 65536) return bfail(b, WCC_EINVAL, "blocks outside [0, 65536]");
   if (threads_per_block) b->threads = threads_per_block;
   b->blocks = blocks;
-  if (mode == 1) b->grouped = false;
-  if (mode == 2) b->grouped = true;
+  if (mode < 0 || mode > 4) return bfail(b, WCC_EINVAL, "schedule mode must be 0..4");
+  if (mode != 0) {
+    b->grouped = mode == 2 || mode == 4;
+    b->staged = mode >= 3;
+  }
   return build_schedule(b);
 }
 

@@ -26,9 +26,12 @@
 
 namespace wcc {
 
-// PF = 1: each wave loads the inputs of its next tile before expanding the
-// current one, so every wave keeps one tile of loads in flight while it
-// computes (costs the registers of one tile's inputs).
+// Variant bits.  PF & 1: each wave loads the inputs of its next tile before
+// expanding the current one, so every wave keeps one tile of loads in flight
+// while it computes (costs the registers of one tile's inputs).  PF & 2: the
+// new cells go through LDS and are stored in whole 64-cell groups (two block
+// barriers per iteration of the block's waves; pays where the state does not
+// fit the caches).
 template <int EQ, int P, bool LIM, class R, int PF>
 __global__ __launch_bounds__(256) void k_half_step(const StepArgs<R> a) {
   double dt;
@@ -45,7 +48,40 @@ __global__ __launch_bounds__(256) void k_half_step(const StepArgs<R> a) {
   const int64_t t_stop = t_begin + per_block < tiles ? t_begin + per_block : tiles;
   double smax = 0.0;
   unsigned flags = 0u;
-  if constexpr (PF == 0) {
+  if constexpr ((PF & 2) != 0) {
+    constexpr int NC = ncomp<EQ>();
+    __shared__ Stage<EQ, P, R> st;
+    int cur = 0;
+    TileIn<EQ, P, R> in;
+    if ((PF & 1) && t_begin + wave < t_stop) fetch_tile<EQ, P, R>(a, t_begin + wave, lane, in);
+    // every wave runs every iteration (the barriers are block-wide)
+    for (int64_t tb = t_begin; tb < t_stop; tb += nw) {
+      const int64_t tile = tb + wave;
+      int lo = 0, hi = 0;
+      if (tile < t_stop) {
+        TileIn<EQ, P, R> nxt;
+        if constexpr ((PF & 1) != 0) {
+          const int64_t t2 = tile + nw < t_stop ? tile + nw : tile;   // in bounds; unused at the end
+          fetch_tile<EQ, P, R>(a, t2, lane, nxt);
+          __builtin_amdgcn_sched_barrier(0);
+        } else {
+          fetch_tile<EQ, P, R>(a, tile, lane, in);
+        }
+        double pn[NC];
+        R dn[NC][P + 1];
+        if (tile_cells<EQ, P, LIM, R>(a, tile, in, lam, nlam, lane, smax, flags, pn, dn))
+          stage_put<EQ, P, R>(st, wave * 64 + lane, pn, dn);
+        if constexpr ((PF & 1) != 0) in = nxt;
+        lo = (int)tile * 63;
+        hi = lo + 63 < (int)a.n_new ? lo + 63 : (int)a.n_new;
+      }
+      __syncthreads();
+      stage_flush<EQ, P, R>(st, cur, wave, nw, lane, lo, hi, tile > t_begin, tile + 1 < t_stop, a.p_new, a.d_new,
+                            a.ld);
+      __syncthreads();
+      cur ^= 1;
+    }
+  } else if constexpr (PF == 0) {
     for (int64_t tile = t_begin + wave; tile < t_stop; tile += nw)
       run_tile<EQ, P, LIM, R>(a, tile, lam, nlam, lane, smax, flags);
   } else {
@@ -97,10 +133,13 @@ __global__ __launch_bounds__(256) void k_state_speed(const StepArgs<R> a) {
 // ---------------------------------------------------------------------------
 template <int EQ, int P, bool LIM, class R>
 static hipError_t launch_one(const StepArgs<R>& a, int pf, int blocks, int threads, hipStream_t s) {
-  if (pf)
-    hipLaunchKernelGGL((k_half_step<EQ, P, LIM, R, 1>), dim3(blocks), dim3(threads), 0, s, a);
-  else
-    hipLaunchKernelGGL((k_half_step<EQ, P, LIM, R, 0>), dim3(blocks), dim3(threads), 0, s, a);
+  switch (pf) {
+    case 0: hipLaunchKernelGGL((k_half_step<EQ, P, LIM, R, 0>), dim3(blocks), dim3(threads), 0, s, a); break;
+    case 1: hipLaunchKernelGGL((k_half_step<EQ, P, LIM, R, 1>), dim3(blocks), dim3(threads), 0, s, a); break;
+    case 2: hipLaunchKernelGGL((k_half_step<EQ, P, LIM, R, 2>), dim3(blocks), dim3(threads), 0, s, a); break;
+    case 3: hipLaunchKernelGGL((k_half_step<EQ, P, LIM, R, 3>), dim3(blocks), dim3(threads), 0, s, a); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 
@@ -161,8 +200,11 @@ hipError_t occupancy_half_step(int eq, int P, bool lim, int pf, int threads, int
   // Queried for the heaviest variant that can run; the kernel is the same for
   // every equation except in register use, so ask for the exact one.
   const void* f = nullptr;
-#define WCC_K(E, PP, L) (pf ? reinterpret_cast<const void*>(&k_half_step<E, PP, L, R, 1>) \
-                            : reinterpret_cast<const void*>(&k_half_step<E, PP, L, R, 0>))
+#define WCC_K(E, PP, L)                                                            \
+  (pf == 3   ? reinterpret_cast<const void*>(&k_half_step<E, PP, L, R, 3>)             \
+   : pf == 2 ? reinterpret_cast<const void*>(&k_half_step<E, PP, L, R, 2>)             \
+   : pf == 1 ? reinterpret_cast<const void*>(&k_half_step<E, PP, L, R, 1>)             \
+             : reinterpret_cast<const void*>(&k_half_step<E, PP, L, R, 0>))
 #define WCC_PSWITCH(E)                                                            \
   switch (P) {                                                                    \
     case 0: f = WCC_K(E, 0, false); break;                                        \

@@ -242,9 +242,12 @@ __device__ __forceinline__ void fetch_tile(const StepArgs<R>& a, int64_t tile, i
   }
 }
 
+// The new cell of this lane (lanes 0..62, cell 63 tile + lane, if it exists):
+// returns whether there is one and leaves it in pn / dn.
 template <int EQ, int P, bool LIM, class R>
-__device__ __forceinline__ void compute_tile(const StepArgs<R>& a, int64_t tile, const TileIn<EQ, P, R>& in,
-                                             double lam, R nlam, int lane, double& smax, unsigned& flags) {
+__device__ __forceinline__ bool tile_cells(const StepArgs<R>& a, int64_t tile, const TileIn<EQ, P, R>& in,
+                                          double lam, R nlam, int lane, double& smax, unsigned& flags,
+                                          double (&pn)[ncomp<EQ>()], R (&dn)[ncomp<EQ>()][P + 1]) {
   constexpr int NC = ncomp<EQ>();
   constexpr int PV = P > 0 ? P : 1;
   OldOut<EQ, P, R> X;
@@ -266,18 +269,124 @@ __device__ __forceinline__ void compute_tile(const StepArgs<R>& a, int64_t tile,
 
   const int j = (int)tile * 63 + lane;
   if (lane < 63 && j < (int)a.n_new) {
-    double pn[NC];
-    R dn[NC][P + 1];
     double sp;
     flags |= (unsigned)new_cell<EQ, P, LIM, R>(X, uL_R, fbar_R, V_R, lam, a.ph, pn, dn, sp);
     smax = __builtin_fmax(smax, sp);
     if (!(sp == sp)) smax = sp;
+    return true;
+  }
+  return false;
+}
+
+template <int EQ, int P, bool LIM, class R>
+__device__ __forceinline__ void compute_tile(const StepArgs<R>& a, int64_t tile, const TileIn<EQ, P, R>& in,
+                                             double lam, R nlam, int lane, double& smax, unsigned& flags) {
+  constexpr int NC = ncomp<EQ>();
+  double pn[NC];
+  R dn[NC][P + 1];
+  if (tile_cells<EQ, P, LIM, R>(a, tile, in, lam, nlam, lane, smax, flags, pn, dn)) {
+    const int j = (int)tile * 63 + lane;
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
       row_store(row_base(a.p_new + c * a.ld), (uint32_t)j, pn[c]);
 #pragma unroll
       for (int k = 1; k <= P; ++k) row_store(row_base(a.d_new + (c * P + (k - 1)) * a.ld), (uint32_t)j, dn[c][k]);
     }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Line-aligned stores.  A tile writes 63 new cells, so every tile edge falls
+// inside a cache line that two waves write in parts; once the state no longer
+// fits the caches such partial-line stores cost a quarter of the HBM
+// bandwidth.  In the staged variants the waves of a block put their new cells
+// into LDS; after a barrier each 64-cell group of new cells (64-aligned, cut
+// to the contiguous run of tiles it lies in) is written whole, by the wave
+// whose tile holds the group's last cell, or by the run's last wave for the
+// run's final group.  A group that the block's next iteration completes is
+// kept in a carry region until then.  The values written are the same.
+// ---------------------------------------------------------------------------
+template <int EQ, int PMAX, class R>
+struct Stage {
+  static constexpr int NC = ncomp<EQ>();
+  static constexpr int ND = NC * (PMAX > 0 ? PMAX : 1);
+  static constexpr int kSlots = 6 * 64;   // wave regions 0..3 (64 slots each), carry regions 4 and 5
+  double p[NC][kSlots];
+  R d[ND][kSlots];
+  int32_t carry_lo[2];                     // first cell held in carry region 4 + i
+};
+
+template <int EQ, int P, class R, class S>
+__device__ __forceinline__ void stage_put(S& s, int slot, const double (&pn)[ncomp<EQ>()],
+                                          const R (&dn)[ncomp<EQ>()][P + 1]) {
+  constexpr int NC = ncomp<EQ>();
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    s.p[c][slot] = pn[c];
+#pragma unroll
+    for (int k = 1; k <= P; ++k) s.d[c * P + (k - 1)][slot] = dn[c][k];
+  }
+}
+
+template <int EQ, int P, class R, class S>
+__device__ __forceinline__ void stage_store(const S& s, int slot, double* p_new, R* d_new, int64_t ld, uint32_t j) {
+  constexpr int NC = ncomp<EQ>();
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    row_store(row_base(p_new + c * ld), j, s.p[c][slot]);
+#pragma unroll
+    for (int k = 1; k <= P; ++k) row_store(row_base(d_new + (c * P + (k - 1)) * ld), j, s.d[c * P + (k - 1)][slot]);
+  }
+}
+
+template <int EQ, int P, class S>
+__device__ __forceinline__ void stage_copy(S& s, int from, int to) {
+  constexpr int NC = ncomp<EQ>();
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    s.p[c][to] = s.p[c][from];
+#pragma unroll
+    for (int k = 1; k <= P; ++k) s.d[c * P + (k - 1)][to] = s.d[c * P + (k - 1)][from];
+  }
+}
+
+// One wave's share of a block iteration's write-out (between the barrier that
+// follows staging and the one before the next staging).
+//   [lo, hi) : the wave's staged cells (region `wave`); lo == hi: none
+//   prev     : the 63 cells below lo are staged by the previous wave, or for
+//              wave 0 the cells from carry_lo[cur] up to lo are in carry
+//              region 4 + cur
+//   next     : the next wave (or, for the last wave, the first wave of the
+//              next iteration) continues the run at hi
+// Every argument is uniform across the wave.
+template <int EQ, int P, class R, class S>
+__device__ __forceinline__ void stage_flush(S& s, int cur, int wave, int nw, int lane, int lo, int hi, bool prev,
+                                            bool next, double* p_new, R* d_new, int64_t ld) {
+  if (lo >= hi) return;
+  int avail = lo;
+  if (prev) {
+    // the carried cells start at most 63 below lo (clamped: every write stays
+    // within the 63 cells below this tile)
+    const int cl = wave > 0 ? lo - 63 : s.carry_lo[cur];
+    avail = cl < lo - 63 ? lo - 63 : (cl > lo ? lo : cl);
+  }
+  auto slot_of = [&](int c) {
+    if (c >= lo) return wave * 64 + (c - lo);
+    return wave > 0 ? (wave - 1) * 64 + (c - (lo - 63)) : (4 + cur) * 64 + (c - avail);
+  };
+  const int e = (hi & ~63) - 1;            // end of the last whole group inside [.., hi)
+  if (e >= lo) {                           // the group ending in this tile
+    const int c = e - 63 + lane;
+    if (c >= avail) stage_store<EQ, P, R>(s, slot_of(c), p_new, d_new, ld, (uint32_t)c);
+  }
+  const int t0 = avail > e + 1 ? avail : e + 1;   // cells after it
+  if (!next) {
+    const int c = t0 + lane;
+    if (c < hi) stage_store<EQ, P, R>(s, slot_of(c), p_new, d_new, ld, (uint32_t)c);
+  } else if (wave == nw - 1) {
+    const int c = t0 + lane;
+    if (c < hi) stage_copy<EQ, P>(s, slot_of(c), (5 - cur) * 64 + lane);
+    if (lane == 0) s.carry_lo[1 - cur] = t0;
   }
 }
 

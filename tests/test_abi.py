@@ -64,6 +64,11 @@ def test_workspace_size_and_state_errors_without_gpu():
     assert lib.wcc_bind(h, None, 0, None) == binding.WCC_EINVAL
     assert lib.wcc_bind(h, ctypes.c_void_p(256), 16, None) == binding.WCC_ESIZE
     assert lib.wcc_bind(h, ctypes.c_void_p(255), nb.value, None) == binding.WCC_EINVAL
+    # kernel variant bits: 1 = prefetch, 2 = staged stores; -1 keeps the current one
+    for v in (-1, 0, 1, 2, 3):
+        assert lib.wcc_set_launch(h, 128, 0, v) == 0
+    assert lib.wcc_set_launch(h, 128, 0, 4) == binding.WCC_EINVAL
+    assert lib.wcc_set_launch(h, 128, 0, -2) == binding.WCC_EINVAL
     lib.wcc_destroy(h)
     pm = binding.make_params(precision="fp32_mixed")
     assert lib.wcc_create(2, 3, 1 << 20, 1, ctypes.byref(pm), ctypes.byref(h)) == 0
@@ -84,6 +89,10 @@ def test_batch_create_validates():
     assert lib.wcc_batch_workspace_bytes(h, ctypes.byref(nb)) == 0 and nb.value > 0
     assert lib.wcc_batch_set_schedule(h, 100, 0, 0) == binding.WCC_EINVAL
     assert lib.wcc_batch_set_schedule(h, 128, 64, 1) == 0
+    for mode in (2, 3, 4, 0):                       # grouped, fused / grouped staged, keep
+        assert lib.wcc_batch_set_schedule(h, 0, 0, mode) == 0
+    assert lib.wcc_batch_set_schedule(h, 0, 0, 5) == binding.WCC_EINVAL
+    assert lib.wcc_batch_set_schedule(h, 0, 0, -1) == binding.WCC_EINVAL
     lib.wcc_batch_destroy(h)
     Pbad = (ctypes.c_int32 * 3)(1, 4, 3)
     assert lib.wcc_batch_create(2, 3, Pbad, N, 1, ctypes.byref(p), ctypes.byref(h)) == binding.WCC_EINVAL
