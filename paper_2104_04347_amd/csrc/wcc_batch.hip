@@ -110,9 +110,14 @@ __device__ __forceinline__ void batch_tile_staged(const BatchArgs<R>& a, const B
 // P < 0: fused schedule (switch on the instance's degree); P >= 0: the
 // grouped schedule's launch for that degree.  STG: staged, line-aligned
 // stores (the block's waves advance in lockstep, two barriers per iteration).
+// Waves per SIMD the compiler must leave room for: the staged degree-1
+// kernel, whose light tiles depend on many waves hiding load latency, is held
+// to 80 registers (6 waves; it needs 83 otherwise); the others are free.
+constexpr int batch_min_waves(int psel, bool stg) { return psel == 1 && stg ? 6 : 1; }
+
 template <int EQ, int PSEL, bool LIM, class R, bool STG>
-__global__ __launch_bounds__(256) void k_batch_step(const BatchArgs<R> a, const int64_t* __restrict__ block_start,
-                                                    int bc) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(batch_min_waves(PSEL, STG))))
+void k_batch_step(const BatchArgs<R> a, const int64_t* __restrict__ block_start, int bc) {
   // the wave index is the same in every lane: say so, so that tile and
   // instance indices live in scalar registers
   const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6),
