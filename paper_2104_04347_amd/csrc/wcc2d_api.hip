@@ -152,13 +152,13 @@ int graph2(wcc2d_ctx* c, int slot0, int parity0, hipGraphExec_t* out) {
   hipGraph_t g = nullptr;
   hipError_t e = hipStreamEndCapture(c->capture, &g);
   if (rc != WCC_OK) {
-    if (g) hipGraphDestroy(g);
+    if (g) (void)hipGraphDestroy(g);
     return rc;
   }
   if (e != hipSuccess) return fail2(c, WCC_EDEVICE, "graph capture: %s", hipGetErrorString(e));
   hipGraphExec_t ex = nullptr;
   e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
-  hipGraphDestroy(g);
+  (void)hipGraphDestroy(g);
   if (e != hipSuccess) return fail2(c, WCC_EDEVICE, "graph instantiate: %s", hipGetErrorString(e));
   c->graphs[key] = ex;
   *out = ex;
@@ -167,7 +167,7 @@ int graph2(wcc2d_ctx* c, int slot0, int parity0, hipGraphExec_t* out) {
 
 void drop_graphs(wcc2d_ctx* c) {
   for (auto& g : c->graphs)
-    if (g) { hipGraphExecDestroy(g); g = nullptr; }
+    if (g) { (void)hipGraphExecDestroy(g); g = nullptr; }
 }
 
 int set_fields(wcc2d_ctx* c, double t_end, double cfl) {
@@ -492,9 +492,9 @@ const char* wcc2d_last_error(const wcc2d_ctx* c) { return c ? c->err.c_str() : "
 void wcc2d_destroy(wcc2d_ctx* c) {
   if (!c) return;
   drop_graphs(c);
-  if (c->capture) hipStreamDestroy(c->capture);
-  if (c->ev0) hipEventDestroy(c->ev0);
-  if (c->ev1) hipEventDestroy(c->ev1);
+  if (c->capture) (void)hipStreamDestroy(c->capture);
+  if (c->ev0) (void)hipEventDestroy(c->ev0);
+  if (c->ev1) (void)hipEventDestroy(c->ev1);
   delete c;
 }
 

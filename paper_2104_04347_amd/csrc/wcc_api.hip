@@ -174,13 +174,13 @@ int chunk_graph(wcc_ctx* c, int slot0, int parity0, hipGraphExec_t* out) {
   hipGraph_t g = nullptr;
   hipError_t e = hipStreamEndCapture(c->capture, &g);
   if (rc != WCC_OK) {
-    if (g) hipGraphDestroy(g);
+    if (g) (void)hipGraphDestroy(g);
     return rc;
   }
   if (e != hipSuccess) return fail(c, WCC_EDEVICE, "graph capture: %s", hipGetErrorString(e));
   hipGraphExec_t ex = nullptr;
   e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
-  hipGraphDestroy(g);
+  (void)hipGraphDestroy(g);
   if (e != hipSuccess) return fail(c, WCC_EDEVICE, "graph instantiate: %s", hipGetErrorString(e));
   c->graphs[key] = ex;
   *out = ex;
@@ -276,7 +276,7 @@ int wcc_bind(wcc_ctx* c, void* dev_ptr, size_t bytes, void* hip_stream) {
   wcc_workspace_bytes(c, &need);
   if (bytes < need) return fail(c, WCC_ESIZE, "workspace of %zu bytes, need %zu", bytes, need);
   for (auto& g : c->graphs)
-    if (g) { hipGraphExecDestroy(g); g = nullptr; }
+    if (g) { (void)hipGraphExecDestroy(g); g = nullptr; }
   c->ws = static_cast<char*>(dev_ptr);
   c->ws_bytes = bytes;
   c->stream = static_cast<hipStream_t>(hip_stream);
@@ -575,7 +575,7 @@ int wcc_set_launch(wcc_ctx* c, int threads_per_block, int blocks, int variant) {
   c->threads = threads_per_block ? threads_per_block : 256;
   c->blocks = blocks;
   for (auto& g : c->graphs)
-    if (g) { hipGraphExecDestroy(g); g = nullptr; }
+    if (g) { (void)hipGraphExecDestroy(g); g = nullptr; }
   return WCC_OK;
 }
 
@@ -596,10 +596,10 @@ const char* wcc_last_error(const wcc_ctx* c) { return c ? c->err.c_str() : "null
 void wcc_destroy(wcc_ctx* c) {
   if (!c) return;
   for (auto& g : c->graphs)
-    if (g) hipGraphExecDestroy(g);
-  if (c->capture) hipStreamDestroy(c->capture);
-  if (c->ev0) hipEventDestroy(c->ev0);
-  if (c->ev1) hipEventDestroy(c->ev1);
+    if (g) (void)hipGraphExecDestroy(g);
+  if (c->capture) (void)hipStreamDestroy(c->capture);
+  if (c->ev0) (void)hipEventDestroy(c->ev0);
+  if (c->ev1) (void)hipEventDestroy(c->ev1);
   delete c;
 }
 

@@ -426,7 +426,7 @@ int build_schedule(wcc_batch* b) {
   }
   b->tables_dirty = true;
   for (auto& g : b->graphs)
-    if (g) { hipGraphExecDestroy(g); g = nullptr; }
+    if (g) { (void)hipGraphExecDestroy(g); g = nullptr; }
   return WCC_OK;
 }
 
@@ -503,13 +503,13 @@ int batch_graph(wcc_batch* b, int slot0, int parity0, hipGraphExec_t* out) {
   hipGraph_t g = nullptr;
   hipError_t e = hipStreamEndCapture(b->capture, &g);
   if (rc != WCC_OK) {
-    if (g) hipGraphDestroy(g);
+    if (g) (void)hipGraphDestroy(g);
     return rc;
   }
   if (e != hipSuccess) return bfail(b, WCC_EDEVICE, "graph capture: %s", hipGetErrorString(e));
   hipGraphExec_t ex = nullptr;
   e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
-  hipGraphDestroy(g);
+  (void)hipGraphDestroy(g);
   if (e != hipSuccess) return bfail(b, WCC_EDEVICE, "graph instantiate: %s", hipGetErrorString(e));
   b->graphs[key] = ex;
   *out = ex;
@@ -588,7 +588,7 @@ int wcc_batch_bind(wcc_batch* b, void* dev_ptr, size_t bytes, void* hip_stream) 
   wcc_batch_workspace_bytes(b, &need);
   if (bytes < need) return bfail(b, WCC_ESIZE, "workspace of %zu bytes, need %zu", bytes, need);
   for (auto& g : b->graphs)
-    if (g) { hipGraphExecDestroy(g); g = nullptr; }
+    if (g) { (void)hipGraphExecDestroy(g); g = nullptr; }
   b->ws = static_cast<char*>(dev_ptr);
   b->ws_bytes = bytes;
   b->stream = static_cast<hipStream_t>(hip_stream);
@@ -847,10 +847,10 @@ const char* wcc_batch_last_error(const wcc_batch* b) { return b ? b->err.c_str()
 void wcc_batch_destroy(wcc_batch* b) {
   if (!b) return;
   for (auto& g : b->graphs)
-    if (g) hipGraphExecDestroy(g);
-  if (b->capture) hipStreamDestroy(b->capture);
-  if (b->ev0) hipEventDestroy(b->ev0);
-  if (b->ev1) hipEventDestroy(b->ev1);
+    if (g) (void)hipGraphExecDestroy(g);
+  if (b->capture) (void)hipStreamDestroy(b->capture);
+  if (b->ev0) (void)hipEventDestroy(b->ev0);
+  if (b->ev1) (void)hipEventDestroy(b->ev1);
   delete b;
 }
 
