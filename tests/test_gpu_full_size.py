@@ -5,11 +5,13 @@ configurations the benchmark times:
   density sine, periodic, CFL 0.20 per half-step -- binary64 bit for bit
   against the FP64 oracle over two half-steps (both mesh parities), and the
   FP32-mixed mode against the same oracle result within the stated
-  tolerance, with its conserved totals at binary64 round-off;
+  tolerance, with its conserved totals at binary64 round-off; with direct
+  and with staged stores (the autotuner picks staged at this size);
 * the batched workload: 4096 instances, N log-uniform in [256, 65536],
   P in {1, 2, 3} -- sampled instances (the smallest, the largest, every
   degree) of the FP32-mixed batch bit for bit against single-instance runs,
-  and of a binary64 batch bit for bit against the oracle;
+  and of a binary64 batch bit for bit against the oracle, in every schedule
+  (fused / grouped, direct / staged stores);
 * the 2D legs: Burgers with the limiter on 2048 x 2048 and the limited Euler
   vortex on 1024 x 1024 (P = 3), bit for bit against the 2D oracle over two
   half-steps.
@@ -50,9 +52,10 @@ def large_case():
     return q0, ref
 
 
-def _large_gpu(q0, precision):
+def _large_gpu(q0, precision, variant=0):
     s = binding.Solver("euler", LARGE_P, LARGE_N, "periodic", limiter=True, precision=precision)
     try:
+        s.set_launch(0, 0, variant)
         s.write(q0)
         tot0 = s.totals()
         s.run(LARGE_STEPS, LARGE_CFL)
@@ -63,23 +66,27 @@ def _large_gpu(q0, precision):
     return q, info, tot0, tot
 
 
+# launch variants: 0 direct stores, 2 staged stores, 3 staged + prefetch (the
+# autotuner's choice at this size)
 @pytest.mark.timeout(600)
-def test_large_fp64_bitwise(large_case):
+@pytest.mark.parametrize("variant", [0, 2, 3])
+def test_large_fp64_bitwise(large_case, variant):
     q0, ref = large_case
-    q, info, _, _ = _large_gpu(q0, "fp64")
+    q, info, _, _ = _large_gpu(q0, "fp64", variant)
     assert info.half_steps == LARGE_STEPS
-    _bitwise(q, info, ref, "large fp64")
+    _bitwise(q, info, ref, f"large fp64 variant {variant}")
 
 
 @pytest.mark.timeout(600)
-def test_large_mixed_within_tolerance(large_case):
+@pytest.mark.parametrize("variant", [0, 3])
+def test_large_mixed_within_tolerance(large_case, variant):
     """Two half-steps in FP32-mixed against the FP64 oracle: point-value L1
     within 4 sqrt(n) u32 S, Linf within 1e-2 S (the weights switch at
     slightly different places in binary32 at the jumps), conserved totals
     within the round-off of their own binary64 evaluation."""
     q0, ref = large_case
-    q, info, tot0, tot = _large_gpu(q0, "fp32_mixed")
-    print("large mixed", flush=True)
+    q, info, tot0, tot = _large_gpu(q0, "fp32_mixed", variant)
+    print(f"large mixed variant {variant}", flush=True)
     assert info.flags & 3 == 0 and info.parity == ref.parity
     n = LARGE_STEPS
     assert abs(info.t - ref.t) <= n * U32 * ref.t
@@ -124,7 +131,7 @@ def _batch_run(spec, precision, mode):
 
 
 @pytest.mark.timeout(600)
-@pytest.mark.parametrize("mode", [1, 2])
+@pytest.mark.parametrize("mode", [1, 2, 3, 4])     # fused / grouped, direct / staged stores
 def test_batch_full_mixed_equals_single(mode):
     spec = inputs.batch_spec(BATCH_B, 0)
     got = _batch_run(spec, "fp32_mixed", mode)
@@ -141,14 +148,15 @@ def test_batch_full_mixed_equals_single(mode):
 
 
 @pytest.mark.timeout(600)
-def test_batch_full_fp64_matches_oracle():
+@pytest.mark.parametrize("mode", [2, 4])
+def test_batch_full_fp64_matches_oracle(mode):
     spec = inputs.batch_spec(BATCH_B, 0)
-    got = _batch_run(spec, "fp64", 2)
+    got = _batch_run(spec, "fp64", mode)
     for b, (qb, ib) in got.items():
         P, N = int(spec.P[b]), int(spec.N[b])
         ref = oracle.run(oracle.Problem("euler", P, N, bc="transmissive", limiter=True),
                          inputs.batch_instance(spec, b), cfl=CFL_BY_P[P], max_half_steps=BATCH_STEPS)
-        _bitwise(qb, ib, ref, f"batch fp64 instance {b} P={P} N={N}")
+        _bitwise(qb, ib, ref, f"batch fp64 mode {mode} instance {b} P={P} N={N}")
 
 
 # ---------------------------------------------------------------------------

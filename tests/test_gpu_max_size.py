@@ -15,7 +15,8 @@ pytestmark = pytest.mark.gpu
 
 
 @pytest.mark.timeout(900)
-def test_1d_max_cells_burgers():
+@pytest.mark.parametrize("variant", [0, 3])      # direct stores; staged stores + prefetch
+def test_1d_max_cells_burgers(variant):
     P, N = 3, 1 << 28
     dx = 2.0 ** -20
     rng = np.random.default_rng(21)
@@ -25,12 +26,13 @@ def test_1d_max_cells_burgers():
         q0[0, k] = (0.1 / k) * (rng.random(N) - 0.5)
     s = binding.Solver("burgers", P, N, "periodic", limiter=True, x_left=0.0, x_right=N * dx)
     try:
+        s.set_launch(0, 0, variant)
         s.write(q0)
         s.step(0.25)
         q, info = s.read()
     finally:
         s.close()
-    print("1D max: GPU step done", flush=True)
+    print(f"1D max, variant {variant}: GPU step done", flush=True)
     assert info.flags & 3 == 0 and info.parity == 1 and q.shape == (1, P + 1, N)
     dt = info.t
     W = 256
