@@ -8,8 +8,9 @@ single-instance runs in both schedules), so the tuner only measures time:
   both, neither) x threads per block (64..256) x blocks per launch
   (multiples of the device's resident-block capacity);
 * batched: schedule mode (fused: one launch per half-step switching on the
-  degree per tile; grouped: one launch per degree; each with or without
-  staged stores) x threads x blocks.
+  degree per tile; grouped: one launch per degree, in sequence or as
+  parallel graph branches; each with or without staged stores) x threads x
+  blocks.
 
 Each candidate is timed with HIP events around graph-replayed half-steps on
 the caller's stream, after a warm-up; the best shape is cached in a JSON file
@@ -127,7 +128,7 @@ def apply_single(solver: "binding.Solver") -> bool:
     return True
 
 
-def tune_batch(batch: "binding.Batch", cfl_by_P, steps: int = 24, modes=(1, 2, 3, 4),
+def tune_batch(batch: "binding.Batch", cfl_by_P, steps: int = 24, modes=(1, 2, 3, 4, 5, 6),
                threads=(128, 256), block_factors=(0, 1, 2, 4), verbose: bool = False) -> dict:
     """Time batched schedules on a batch whose instances are written and
     prepared.  Candidates run consecutively from the evolving state (the cost

@@ -15,7 +15,10 @@
 // of one instance into one wave-level speed reduction and one atomic.  Either
 // schedule can stage the new cells in LDS and store them in whole 64-cell
 // groups (runs of consecutive tiles of one instance), which keeps partial
-// cache-line stores off HBM when the batch does not fit the caches.
+// cache-line stores off HBM when the batch does not fit the caches.  The
+// grouped schedule can also capture each degree's launches as a branch of
+// its own in the run's graphs: instances of different degrees never depend
+// on each other, so their launches may overlap and fill each other's tails.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -307,6 +310,7 @@ struct wcc_batch {
   // schedule
   bool grouped = true;
   bool staged = false;                   // line-aligned stores through LDS
+  bool branches = false;                 // grouped: the degrees' launches as parallel graph branches
   int threads = 256, blocks = 0, cu = 256;
   std::vector<int64_t> block_start;      // fused: blocks+1 entries; grouped: per group blocks+1 entries, concatenated
   std::vector<int> group_blocks;         // grouped: blocks per degree
@@ -324,6 +328,8 @@ struct wcc_batch {
   bool bound = false, tables_dirty = true;
   int64_t launched = 0;
   hipStream_t capture = nullptr;
+  hipStream_t branch[wcc::kBatchPMax + 1] = {};   // capture-time streams of the degree branches
+  hipEvent_t fork = nullptr, join[wcc::kBatchPMax + 1] = {};
   hipGraphExec_t graphs[6] = {};
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   std::string err;
@@ -453,8 +459,10 @@ int upload_tables(wcc_batch* b) {
   return WCC_OK;
 }
 
+// One half-step of every instance on stream s; with only_p >= 0 (grouped
+// schedule) just the launch of that degree.
 template <class R>
-int enqueue_batch_step(wcc_batch* b, int parity, int slot, hipStream_t s) {
+int enqueue_batch_step(wcc_batch* b, int parity, int slot, hipStream_t s, int only_p = -1) {
   BatchArgs<R> a{};
   a.p_in = b->p[parity];
   a.d_in = static_cast<const R*>(b->d[parity]);
@@ -478,6 +486,10 @@ int enqueue_batch_step(wcc_batch* b, int parity, int slot, hipStream_t s) {
   for (int p = 0; p <= wcc::kBatchPMax; ++p) {
     const int nb = b->group_blocks[p];
     if (nb == 0) continue;
+    if (only_p >= 0 && p != only_p) {
+      off += (size_t)nb + 1;
+      continue;
+    }
     hipError_t e = wcc::launch_batch<R>(a, b->d_bs + off, b->eq, b->bc, p, lim, b->staged, nb, b->threads, s);
     if (e != hipSuccess) return bfail(b, WCC_EDEVICE, "batch launch (P=%d): %s", p, hipGetErrorString(e));
     off += (size_t)nb + 1;
@@ -485,9 +497,37 @@ int enqueue_batch_step(wcc_batch* b, int parity, int slot, hipStream_t s) {
   return WCC_OK;
 }
 
-int enqueue_b(wcc_batch* b, int parity, int slot, hipStream_t s) {
-  return b->prm.precision == WCC_FP64 ? enqueue_batch_step<double>(b, parity, slot, s)
-                                      : enqueue_batch_step<float>(b, parity, slot, s);
+int enqueue_b(wcc_batch* b, int parity, int slot, hipStream_t s, int only_p = -1) {
+  return b->prm.precision == WCC_FP64 ? enqueue_batch_step<double>(b, parity, slot, s, only_p)
+                                      : enqueue_batch_step<float>(b, parity, slot, s, only_p);
+}
+
+// Capture a chunk with one graph branch per degree: the instances of one
+// degree depend only on their own previous half-steps, so the launches of
+// different degrees may run side by side (filling each other's tails).
+int capture_branches(wcc_batch* b, int slot0, int parity0) {
+  if (!b->fork) BHIP(b, hipEventCreateWithFlags(&b->fork, hipEventDisableTiming));
+  BHIP(b, hipEventRecord(b->fork, b->capture));
+  for (int p = 0; p <= wcc::kBatchPMax; ++p) {
+    if (b->group_blocks[p] == 0) continue;
+    if (!b->branch[p]) BHIP(b, hipStreamCreateWithFlags(&b->branch[p], hipStreamNonBlocking));
+    if (!b->join[p]) BHIP(b, hipEventCreateWithFlags(&b->join[p], hipEventDisableTiming));
+    BHIP(b, hipStreamWaitEvent(b->branch[p], b->fork, 0));
+  }
+  int rc = WCC_OK;
+  for (int p = 0; p <= wcc::kBatchPMax && rc == WCC_OK; ++p) {
+    if (b->group_blocks[p] == 0) continue;
+    for (int i = 0; i < kBatchChunk && rc == WCC_OK; ++i)
+      rc = enqueue_b(b, (parity0 + i) & 1, (slot0 + i) % 3, b->branch[p], p);
+  }
+  // join every branch back into the capturing stream (also after an error,
+  // so that the capture can end)
+  for (int p = 0; p <= wcc::kBatchPMax; ++p) {
+    if (b->group_blocks[p] == 0) continue;
+    BHIP(b, hipEventRecord(b->join[p], b->branch[p]));
+    BHIP(b, hipStreamWaitEvent(b->capture, b->join[p], 0));
+  }
+  return rc;
 }
 
 int batch_graph(wcc_batch* b, int slot0, int parity0, hipGraphExec_t* out) {
@@ -499,7 +539,11 @@ int batch_graph(wcc_batch* b, int slot0, int parity0, hipGraphExec_t* out) {
   if (!b->capture) BHIP(b, hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking));
   BHIP(b, hipStreamBeginCapture(b->capture, hipStreamCaptureModeThreadLocal));
   int rc = WCC_OK;
-  for (int i = 0; i < kBatchChunk && rc == WCC_OK; ++i) rc = enqueue_b(b, (parity0 + i) & 1, (slot0 + i) % 3, b->capture);
+  if (b->grouped && b->branches)
+    rc = capture_branches(b, slot0, parity0);
+  else
+    for (int i = 0; i < kBatchChunk && rc == WCC_OK; ++i)
+      rc = enqueue_b(b, (parity0 + i) & 1, (slot0 + i) % 3, b->capture);
   hipGraph_t g = nullptr;
   hipError_t e = hipStreamEndCapture(b->capture, &g);
   if (rc != WCC_OK) {
@@ -824,10 +868,11 @@ int wcc_batch_set_schedule(wcc_batch* b, int threads_per_block, int blocks, int 
   if (blocks < 0 || blocks > 65536) return bfail(b, WCC_EINVAL, "blocks outside [0, 65536]");
   if (threads_per_block) b->threads = threads_per_block;
   b->blocks = blocks;
-  if (mode < 0 || mode > 4) return bfail(b, WCC_EINVAL, "schedule mode must be 0..4");
+  if (mode < 0 || mode > 6) return bfail(b, WCC_EINVAL, "schedule mode must be 0..6");
   if (mode != 0) {
-    b->grouped = mode == 2 || mode == 4;
-    b->staged = mode >= 3;
+    b->grouped = mode == 2 || mode == 4 || mode >= 5;
+    b->staged = mode == 3 || mode == 4 || mode == 6;
+    b->branches = mode >= 5;
   }
   return build_schedule(b);
 }
@@ -849,6 +894,11 @@ void wcc_batch_destroy(wcc_batch* b) {
   for (auto& g : b->graphs)
     if (g) (void)hipGraphExecDestroy(g);
   if (b->capture) (void)hipStreamDestroy(b->capture);
+  for (int p = 0; p <= wcc::kBatchPMax; ++p) {
+    if (b->branch[p]) (void)hipStreamDestroy(b->branch[p]);
+    if (b->join[p]) (void)hipEventDestroy(b->join[p]);
+  }
+  if (b->fork) (void)hipEventDestroy(b->fork);
   if (b->ev0) (void)hipEventDestroy(b->ev0);
   if (b->ev1) (void)hipEventDestroy(b->ev1);
   delete b;

@@ -89,9 +89,9 @@ def test_batch_create_validates():
     assert lib.wcc_batch_workspace_bytes(h, ctypes.byref(nb)) == 0 and nb.value > 0
     assert lib.wcc_batch_set_schedule(h, 100, 0, 0) == binding.WCC_EINVAL
     assert lib.wcc_batch_set_schedule(h, 128, 64, 1) == 0
-    for mode in (2, 3, 4, 0):                       # grouped, fused / grouped staged, keep
+    for mode in (2, 3, 4, 5, 6, 0):                 # grouped, fused / grouped staged, branches, keep
         assert lib.wcc_batch_set_schedule(h, 0, 0, mode) == 0
-    assert lib.wcc_batch_set_schedule(h, 0, 0, 5) == binding.WCC_EINVAL
+    assert lib.wcc_batch_set_schedule(h, 0, 0, 7) == binding.WCC_EINVAL
     assert lib.wcc_batch_set_schedule(h, 0, 0, -1) == binding.WCC_EINVAL
     lib.wcc_batch_destroy(h)
     Pbad = (ctypes.c_int32 * 3)(1, 4, 3)

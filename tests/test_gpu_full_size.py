@@ -11,7 +11,8 @@ configurations the benchmark times:
   P in {1, 2, 3} -- sampled instances (the smallest, the largest, every
   degree) of the FP32-mixed batch bit for bit against single-instance runs,
   and of a binary64 batch bit for bit against the oracle, in every schedule
-  (fused / grouped, direct / staged stores);
+  (fused / grouped, direct / staged stores, degrees in sequence or as
+  parallel graph branches);
 * the 2D legs: Burgers with the limiter on 2048 x 2048 and the limited Euler
   vortex on 1024 x 1024 (P = 3), bit for bit against the 2D oracle over two
   half-steps.
@@ -131,7 +132,7 @@ def _batch_run(spec, precision, mode):
 
 
 @pytest.mark.timeout(600)
-@pytest.mark.parametrize("mode", [1, 2, 3, 4])     # fused / grouped, direct / staged stores
+@pytest.mark.parametrize("mode", [1, 2, 3, 4, 5, 6])   # fused / grouped, direct / staged, branches
 def test_batch_full_mixed_equals_single(mode):
     spec = inputs.batch_spec(BATCH_B, 0)
     got = _batch_run(spec, "fp32_mixed", mode)
@@ -148,7 +149,7 @@ def test_batch_full_mixed_equals_single(mode):
 
 
 @pytest.mark.timeout(600)
-@pytest.mark.parametrize("mode", [2, 4])
+@pytest.mark.parametrize("mode", [2, 4, 6])
 def test_batch_full_fp64_matches_oracle(mode):
     spec = inputs.batch_spec(BATCH_B, 0)
     got = _batch_run(spec, "fp64", mode)

@@ -117,7 +117,7 @@ def _batch(precision, mode, spec, qs, steps, threads=256, blocks=0):
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32_mixed"])
-@pytest.mark.parametrize("mode", [3, 4])
+@pytest.mark.parametrize("mode", [3, 4, 5, 6])
 @pytest.mark.parametrize("threads,blocks", [(256, 0), (64, 5), (192, 3), (128, 40)])
 def test_batch_staged_equals_direct(precision, mode, threads, blocks):
     """Batches with instances of every degree and sizes around the tile and
