@@ -275,8 +275,12 @@ def time_large(args):
     finals = {}
     for prec in ("fp32_mixed", "fp64"):
         s = binding.Solver("euler", P, N, "periodic", limiter=True, precision=prec)
-        # kernel variant only (a short tune: each candidate costs ~1 ms per half-step)
-        shape = launch_shape_single(args, s, q0, cfl, steps=96, threads=(256,), block_factors=(0,))
+        if args.large_variant >= 0:
+            s.set_launch(256, 0, args.large_variant)
+            shape = {"threads": 256, "blocks": 0, "variant": args.large_variant, "source": "--large-variant"}
+        else:
+            # kernel variant only (a short tune: each candidate costs ~1 ms per half-step)
+            shape = launch_shape_single(args, s, q0, cfl, steps=96, threads=(256,), block_factors=(0,))
         s.write(q0)
         tot0 = s.totals()
         torch.cuda.synchronize()
@@ -365,6 +369,8 @@ def main():
     ap.add_argument("--large", action="store_true", help="also run the large 16.7M-cell P=4 workload")
     ap.add_argument("--large-N", type=int, default=1 << 24)
     ap.add_argument("--large-steps", type=int, default=10000)
+    ap.add_argument("--large-variant", type=int, default=-1, choices=(-1, 0, 1, 2, 3),
+                    help="launch variant of the large workload (256 threads, default grid); -1: per --tune")
     ap.add_argument("--tune", choices=("auto", "force", "off"), default="auto",
                     help="launch shapes: cached autotuner result else tune (auto), always tune, or library default")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
