@@ -142,3 +142,59 @@ def test_batch_staged_fp64_matches_oracle():
         ref = oracle.run(oracle.Problem("euler", P, N, bc="transmissive", limiter=True), q, cfl=cfl[P],
                          max_half_steps=15)
         assert got[b][1].t == ref.t and np.array_equal(got[b][0], ref.q), b
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_mixed"])
+@pytest.mark.parametrize("mode", [1, 3, 4, 5, 6])
+def test_batch_graphs_equal_direct(precision, mode):
+    """50 half-steps: two captured 24-half-step graphs (with one branch per
+    degree in modes 5 and 6) and two enqueued half-steps, against the
+    grouped direct schedule run the same way, and each instance's time
+    against its single-instance run."""
+    spec = inputs.batch_spec(12, 13, n_lo=40, n_hi=1500)
+    spec.N[:4] = [2, 63, 64, 127]
+    qs = [inputs.batch_instance(spec, b) for b in range(spec.P.size)]
+    got = _batch(precision, mode, spec, qs, 50)
+    ref = _batch(precision, 2, spec, qs, 50)
+    cfl = [0.4, 0.4, 0.3, 0.25, 0.25]
+    for b in range(spec.P.size):
+        assert got[b][1].half_steps == 50 and got[b][1].t == ref[b][1].t, b
+        assert np.array_equal(got[b][0], ref[b][0]), f"instance {b} (P={spec.P[b]}, N={spec.N[b]})"
+    # one instance of every degree against its own single-instance run
+    for P in (1, 2, 3):
+        b = int(np.flatnonzero(spec.P == P)[0])
+        s = binding.Solver("euler", P, int(spec.N[b]), "transmissive", limiter=True, precision=precision)
+        try:
+            s.write(qs[b])
+            s.run(50, cfl[P])
+            q1, i1 = s.read()
+        finally:
+            s.close()
+        assert i1.t == got[b][1].t and np.array_equal(q1, got[b][0]), f"instance {b} vs single"
+
+
+@pytest.mark.parametrize("mode", [5, 6])
+def test_batch_branches_single_degree(mode):
+    """Parallel degree branches with only one degree present (one branch)."""
+    spec = inputs.batch_spec(6, 14, n_lo=40, n_hi=900, degrees=(2,))
+    qs = [inputs.batch_instance(spec, b) for b in range(spec.P.size)]
+    got = _batch("fp64", mode, spec, qs, 30)
+    ref = _batch("fp64", 2, spec, qs, 30)
+    for b in range(spec.P.size):
+        assert got[b][1].t == ref[b][1].t and np.array_equal(got[b][0], ref[b][0]), b
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_mixed"])
+@pytest.mark.parametrize("variant", STAGED)
+def test_graph_replay_equals_direct(precision, variant):
+    """100 half-steps: two captured 48-half-step graphs and four enqueued
+    launches in a staged variant, bit for bit against variant 0 run the
+    same way, on a mesh whose block ranges end inside 64-cell groups."""
+    N = 20011
+    q0, _ = inputs.euler_riemann(5, 3, N)
+    q, info = run_gpu("euler", 3, N, "transmissive", q0, 100, 0.25, variant=variant, threads=192, blocks=37,
+                      precision=precision)
+    r, rinfo = run_gpu("euler", 3, N, "transmissive", q0, 100, 0.25, variant=0, threads=192, blocks=37,
+                       precision=precision)
+    assert info.half_steps == 100 and info.t == rinfo.t and info.parity == rinfo.parity
+    assert np.array_equal(q, r)
