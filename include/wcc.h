@@ -189,8 +189,8 @@ int wcc_batch_read_dofs(wcc_batch* bt, int b, double* host, int64_t cap, wcc_sta
  * current value), blocks per launch (0 = fill the device at the kernel's
  * occupancy) and mode (0 keeps the current one; 1 = fused: one launch per
  * half-step over all tiles, degree switched per tile; 2 = grouped: one launch
- * per degree per half-step (the default); 3 and 4 = fused and grouped with
- * the new cells staged in LDS and stored in whole 64-cell groups; 5 and 6 =
+ * per degree per half-step; 3 and 4 = fused and grouped with the new cells
+ * staged in LDS and stored in whole 64-cell groups; 5 (the default) and 6 =
  * grouped with direct / staged stores, the degrees' launches captured as
  * parallel branches of the run's graphs so that they may overlap on the
  * device; other values return WCC_EINVAL).  Results do not depend on the

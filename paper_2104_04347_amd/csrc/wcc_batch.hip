@@ -310,7 +310,7 @@ struct wcc_batch {
   // schedule
   bool grouped = true;
   bool staged = false;                   // line-aligned stores through LDS
-  bool branches = false;                 // grouped: the degrees' launches as parallel graph branches
+  bool branches = true;                  // grouped: the degrees' launches as parallel graph branches
   int threads = 256, blocks = 0, cu = 256;
   std::vector<int64_t> block_start;      // fused: blocks+1 entries; grouped: per group blocks+1 entries, concatenated
   std::vector<int> group_blocks;         // grouped: blocks per degree
