@@ -82,7 +82,7 @@ def launch_shape_single(args, s, q0, cfl=None, **tune_kw) -> dict:
     the library's default).  Results do not depend on the shape."""
     from paper_2104_04347_amd import autotune
     if args.tune == "off":
-        return {"threads": 0, "blocks": 0, "variant": 0, "source": "library default"}
+        return {**s.get_launch(), "source": "library default"}
     if args.tune == "auto" and autotune.apply_single(s):
         c = autotune.cached_single(s)
         return {"threads": c["threads"], "blocks": c["blocks"], "variant": c.get("variant", 0),

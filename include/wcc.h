@@ -152,10 +152,16 @@ int wcc_totals(wcc_ctx* ctx, double* per_component);
  * occupancy) and kernel variant, a sum of bits: 1 = load the next tile's
  * inputs while computing the current one; 2 = store the new cells in whole
  * 64-cell groups staged through LDS instead of one 63-cell tile per wave
- * (pays when the state does not fit the caches).  0 (the default) is
- * neither; -1 keeps the current variant; values outside -1..3 return
- * WCC_EINVAL.  Used by the autotuner; results do not depend on it. */
+ * (pays when the state does not fit the caches); 0 is neither; -1 keeps the
+ * current variant; values outside -1..3 return WCC_EINVAL.  At creation the
+ * variant is 3 when the two state buffers exceed 512 MiB, else 1.  Used by
+ * the autotuner; results do not depend on it. */
 int wcc_set_launch(wcc_ctx* ctx, int threads_per_block, int blocks, int variant);
+
+/* The current launch shape: threads per block, blocks (0 = device-filling
+ * default) and kernel variant, as wcc_set_launch describes them.  Returns
+ * WCC_EINVAL for a NULL argument. */
+int wcc_get_launch(const wcc_ctx* ctx, int* threads_per_block, int* blocks, int* variant);
 
 /* Number of kernel launches and the device time of the last wcc_run call
  * (HIP events around the enqueued work on the bound stream), in ms. */

@@ -66,6 +66,7 @@ def tune_single(solver: "binding.Solver", q0: np.ndarray, cfl: float, steps: int
     library's default (resident-block capacity)."""
     import torch
     cu = torch.cuda.get_device_properties(0).multi_processor_count
+    default = solver.get_launch()          # the library's choice for this size
     results = []
     for var in variants:
         for th in threads:
@@ -81,7 +82,7 @@ def tune_single(solver: "binding.Solver", q0: np.ndarray, cfl: float, steps: int
                 if verbose:
                     print(f"  variant={var} threads={th:4d} blocks={blocks:6d}: {ms / steps * 1e3:8.2f} us/half-step",
                           flush=True)
-    solver.set_launch(0, 0, 0)
+    solver.set_launch(default["threads"], default["blocks"], default["variant"])
     solver.write(q0)
     solver.run(48, cfl)
     torch.cuda.synchronize()
@@ -89,7 +90,7 @@ def tune_single(solver: "binding.Solver", q0: np.ndarray, cfl: float, steps: int
     default_ms = solver.last_run_ms() / steps
     best = min(results, key=lambda r: r["ms_per_step"])
     if default_ms <= best["ms_per_step"]:
-        best = {"variant": 0, "threads": 0, "blocks": 0, "ms_per_step": default_ms}
+        best = {**default, "ms_per_step": default_ms}
     best["default_ms_per_step"] = default_ms
     best["per_variant_ms"] = {v: min(r["ms_per_step"] for r in results if r["variant"] == v) for v in variants}
     best["tried"] = results

@@ -80,6 +80,7 @@ SIGNATURES = {
     "wcc_read_dofs": ([_vp, _dp, _i64, _c.POINTER(wcc_state_info)], _c.c_int),
     "wcc_totals": ([_vp, _dp], _c.c_int),
     "wcc_set_launch": ([_vp, _c.c_int, _c.c_int, _c.c_int], _c.c_int),
+    "wcc_get_launch": ([_vp, _c.POINTER(_c.c_int), _c.POINTER(_c.c_int), _c.POINTER(_c.c_int)], _c.c_int),
     "wcc_last_run_ms": ([_vp, _dp], _c.c_int),
     "wcc_strerror": ([_c.c_int], _c.c_char_p),
     "wcc_last_error": ([_vp], _c.c_char_p),
@@ -242,6 +243,12 @@ class Solver:
 
     def set_launch(self, threads: int = 0, blocks: int = 0, variant: int = -1) -> None:
         _check(load().wcc_set_launch(self.h, int(threads), int(blocks), int(variant)), "wcc_set_launch", self.h)
+
+    def get_launch(self) -> dict:
+        """The current launch shape: threads per block, blocks (0 = default) and kernel variant."""
+        t, b, v = _c.c_int(), _c.c_int(), _c.c_int()
+        _check(load().wcc_get_launch(self.h, _c.byref(t), _c.byref(b), _c.byref(v)), "wcc_get_launch", self.h)
+        return {"threads": t.value, "blocks": b.value, "variant": v.value}
 
     def last_run_ms(self) -> float:
         ms = ctypes.c_double()

@@ -57,7 +57,7 @@ struct wcc_ctx {
   int64_t launched = 0;     // kernels enqueued since the write (slot = launched % 3)
   int64_t steps = 0;        // half-steps known to be done (exact after a sync)
   int threads = 256, blocks = 0;
-  int prefetch = 0;          // kernel variant bits: 1 = prefetch the next tile's inputs, 2 = aligned stores
+  int prefetch = 1;          // kernel variant bits: 1 = prefetch the next tile's inputs, 2 = aligned stores
   int cu = 0;
   hipStream_t capture = nullptr;
   hipGraphExec_t graphs[6] = {};
@@ -251,6 +251,12 @@ int wcc_create(int equation, int P, int64_t N, int bc, const wcc_params* params,
   c->elem = prm.precision == WCC_FP64 ? 8 : 4;
   const int64_t nmax = std::max(ncells_of(c, 0), ncells_of(c, 1));
   c->ld = (nmax + 63) / 64 * 64;
+  // Default kernel variant by state size (measured on MI355X, P = 3 and 4,
+  // both precisions): once the two state buffers outgrow the 256 MB Infinity
+  // Cache by about a factor two, the staged stores with prefetch are fastest
+  // (the crossover lies between 0.50 and 0.60 GB); below, prefetch alone.
+  const double state_bytes = 2.0 * (double)c->nc * (double)c->ld * (8.0 + (double)(c->P * c->elem));
+  c->prefetch = state_bytes > 512.0 * 1048576.0 ? 3 : 1;
   int dev = 0;
   if (hipGetDevice(&dev) == hipSuccess) {
     hipDeviceProp_t prop;
@@ -562,6 +568,14 @@ int wcc_totals(wcc_ctx* c, double* per_component) {
     }
     per_component[cc] = tot * info.dx;
   }
+  return WCC_OK;
+}
+
+int wcc_get_launch(const wcc_ctx* c, int* threads_per_block, int* blocks, int* variant) {
+  if (!c || !threads_per_block || !blocks || !variant) return WCC_EINVAL;
+  *threads_per_block = c->threads;
+  *blocks = c->blocks;
+  *variant = c->prefetch;
   return WCC_OK;
 }
 

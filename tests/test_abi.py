@@ -64,9 +64,21 @@ def test_workspace_size_and_state_errors_without_gpu():
     assert lib.wcc_bind(h, None, 0, None) == binding.WCC_EINVAL
     assert lib.wcc_bind(h, ctypes.c_void_p(256), 16, None) == binding.WCC_ESIZE
     assert lib.wcc_bind(h, ctypes.c_void_p(255), nb.value, None) == binding.WCC_EINVAL
+    # default variant by state size: prefetch (1) below 512 MiB of state
+    t, b, v = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    assert lib.wcc_get_launch(h, ctypes.byref(t), ctypes.byref(b), ctypes.byref(v)) == 0
+    assert (t.value, b.value, v.value) == (256, 0, 1)
+    assert lib.wcc_get_launch(h, None, ctypes.byref(b), ctypes.byref(v)) == binding.WCC_EINVAL
     # kernel variant bits: 1 = prefetch, 2 = staged stores; -1 keeps the current one
-    for v in (-1, 0, 1, 2, 3):
-        assert lib.wcc_set_launch(h, 128, 0, v) == 0
+    for v_ in (-1, 0, 1, 2, 3):
+        assert lib.wcc_set_launch(h, 128, 0, v_) == 0
+    assert lib.wcc_get_launch(h, ctypes.byref(t), ctypes.byref(b), ctypes.byref(v)) == 0
+    assert (t.value, b.value, v.value) == (128, 0, 3)
+    # 2^24 cells of Euler P = 4 in binary64: 4 GB of state -> staged stores + prefetch
+    big = ctypes.c_void_p()
+    assert lib.wcc_create(2, 4, 1 << 24, 0, ctypes.byref(p), ctypes.byref(big)) == 0
+    assert lib.wcc_get_launch(big, ctypes.byref(t), ctypes.byref(b), ctypes.byref(v)) == 0 and v.value == 3
+    lib.wcc_destroy(big)
     assert lib.wcc_set_launch(h, 128, 0, 4) == binding.WCC_EINVAL
     assert lib.wcc_set_launch(h, 128, 0, -2) == binding.WCC_EINVAL
     lib.wcc_destroy(h)
