@@ -13,9 +13,10 @@ configurations the benchmark times:
   and of a binary64 batch bit for bit against the oracle, in every schedule
   (fused / grouped, direct / staged stores, degrees in sequence or as
   parallel graph branches);
-* the 2D legs: Burgers with the limiter on 2048 x 2048 and the limited Euler
-  vortex on 1024 x 1024 (P = 3), bit for bit against the 2D oracle over two
-  half-steps.
+* the 2D legs: Burgers with the limiter on 2048 x 2048, the Euler vortex on
+  1024 x 1024 unlimited and limited, and the first 2D Riemann problem on
+  1200 x 1200 intervals with transmissive edges (P = 3), bit for bit against
+  the 2D oracle over two half-steps.
 """
 import numpy as np
 import pytest
@@ -164,17 +165,23 @@ def test_batch_full_fp64_matches_oracle(mode):
 # 2D legs
 # ---------------------------------------------------------------------------
 @pytest.mark.timeout(600)
-@pytest.mark.parametrize("case", ["burgers_lim_P3_2048", "euler_vortex_lim_P3_1024"])
+@pytest.mark.parametrize("case", ["burgers_lim_P3_2048", "euler_vortex_P3_1024", "euler_vortex_lim_P3_1024",
+                                  "riemann2d_1_lim_P3_1200"])
 def test_2d_bench_size_bitwise(case):
-    P = 3
+    """Every 2D benchmark leg at its benchmark size and in the library's
+    default launch (row marching with prefetch), two half-steps."""
+    P, lim, bc = 3, "_lim_" in case, "periodic"
     if case.startswith("burgers"):
         eq, N, dom = "burgers", 2048, (0.0, 2.0, 0.0, 2.0)
         q0 = inputs.taylor2d(inputs.modes2d(0), P, N, N)
-    else:
+    elif case.startswith("euler_vortex"):
         eq, N, dom = "euler", 1024, (-5.0, 5.0, -5.0, 5.0)
         q0 = inputs.isentropic_vortex(P, N)
+    else:
+        eq, N, dom, bc = "euler", 1200, (-1.0, 1.0, -1.0, 1.0), "transmissive"
+        q0 = inputs.riemann2d(1, P, N)
     kw = dict(x_left=dom[0], x_right=dom[1], y_left=dom[2], y_right=dom[3])
-    s = binding.Solver2D(eq, P, N, N, limiter=True, **kw)
+    s = binding.Solver2D(eq, P, N, N, limiter=lim, bc=bc, **kw)
     try:
         s.write(q0)
         s.run(2, 0.25)
@@ -182,5 +189,5 @@ def test_2d_bench_size_bitwise(case):
     finally:
         s.close()
     print(f"{case}: oracle", flush=True)
-    ref = oracle.run2d(oracle.Problem2D(eq, P, N, N, limiter=True, **kw), q0, cfl=0.25, max_half_steps=2)
+    ref = oracle.run2d(oracle.Problem2D(eq, P, N, N, limiter=lim, bc=bc, **kw), q0, cfl=0.25, max_half_steps=2)
     _bitwise(q, info, ref, case)
