@@ -7,12 +7,14 @@
 //     overlap between neighbouring tiles: 1/64 redundant expansion work);
 //   * every lane expands its own old cell (Cauchy-Kovalewski in registers),
 //     then takes the right parent's half of the interface data from lane+1
-//     with DPP wave_shl:1 row moves -- no LDS, no barrier;
+//     with DPP wave_shl:1 row moves -- no LDS, no barrier (the staged
+//     variants add LDS and two block barriers per iteration for the stores);
 //   * a block owns a contiguous run of tiles (its waves walk it four apart),
 //     so neighbouring tiles share cache lines inside one CU / XCD;
 //   * the state is structure of arrays: point values [c][j] in binary64 and
 //     derivatives [c][k-1][j] in the bulk type, rows padded to 64 cells, so
-//     every load and store of a wave is a contiguous 256/512-byte segment.
+//     every load and store of a wave is a contiguous 256/512-byte segment
+//     (64-aligned in the staged variants).
 // Time control is on the device: the kernel reads t and s_max from a ring of
 // three slots, writes the next time to the next slot, max-reduces its wave
 // speeds into the next slot and clears the slot after that, so consecutive

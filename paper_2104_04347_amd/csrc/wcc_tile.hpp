@@ -1,7 +1,8 @@
 // wcc_tile.hpp -- wave-level building blocks shared by the single-instance and
 // batched half-step kernels: lane exchange by DPP, wave/block reductions, the
-// device-side time step and the body that turns one tile of 64 old cells into
-// 63 new cells.
+// device-side time step, the body that turns one tile of 64 old cells into
+// 63 new cells, and the LDS staging that stores new cells in whole 64-cell
+// groups.
 #pragma once
 
 #include <hip/hip_runtime.h>
