@@ -198,3 +198,41 @@ def test_graph_replay_equals_direct(precision, variant):
                        precision=precision)
     assert info.half_steps == 100 and info.t == rinfo.t and info.parity == rinfo.parity
     assert np.array_equal(q, r)
+
+
+@pytest.mark.parametrize("mode", [4, 6])
+def test_batch_periodic_staged(mode):
+    """Periodic instances (N cells on both meshes), 30 half-steps (one graph
+    chunk + 6 launches): staged schedules against the grouped direct one and
+    an instance of every degree against its single-instance run."""
+    spec = inputs.batch_spec(9, 15, n_lo=40, n_hi=1200)
+    spec.N[:3] = [2, 63, 65]
+    qs = [inputs.euler_riemann(int(spec.seeds[b]), int(spec.P[b]), int(spec.N[b]), bc="periodic")[0]
+          for b in range(spec.P.size)]
+    cfl = [0.4, 0.4, 0.3, 0.25, 0.25]
+
+    def run(m):
+        bt = binding.Batch("euler", spec.P, spec.N, "periodic", limiter=True, precision="fp64")
+        try:
+            bt.set_schedule(256, 0, m)
+            for b, q in enumerate(qs):
+                bt.write(b, q)
+            bt.prepare()
+            bt.run(30, cfl)
+            return [bt.read(b) for b in range(spec.P.size)]
+        finally:
+            bt.close()
+
+    got, ref = run(mode), run(2)
+    for b in range(spec.P.size):
+        assert got[b][1].t == ref[b][1].t and np.array_equal(got[b][0], ref[b][0]), b
+    for P in (1, 2, 3):
+        b = int(np.flatnonzero(spec.P == P)[0])
+        s = binding.Solver("euler", P, int(spec.N[b]), "periodic", limiter=True, precision="fp64")
+        try:
+            s.write(qs[b])
+            s.run(30, cfl[P])
+            q1, i1 = s.read()
+        finally:
+            s.close()
+        assert i1.t == got[b][1].t and np.array_equal(q1, got[b][0]), f"instance {b} vs single"
