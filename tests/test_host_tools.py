@@ -113,3 +113,53 @@ def test_gpu_count_guard():
     r = subprocess.run([sys.executable, os.path.join(bench.ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
                        text=True, timeout=120)
     assert r.returncode == 2 and "one GPU" in r.stderr
+
+
+class _FakeSolver:
+    """Stands in for binding.Solver: scripted per-shape timings, no GPU."""
+    equation, P, N = "euler", 3, 1 << 20
+
+    class params:
+        precision, limiter = 0, 1
+
+    def __init__(self, times, default):
+        self.times, self.shape, self.calls = times, dict(default), []
+
+    def get_launch(self):
+        return dict(self.shape)
+
+    def set_launch(self, threads=0, blocks=0, variant=-1):
+        self.shape = {"threads": threads or 256, "blocks": blocks,
+                      "variant": self.shape["variant"] if variant < 0 else variant}
+        self.calls.append(dict(self.shape))
+
+    def write(self, q0):
+        pass
+
+    def run(self, steps, cfl):
+        self.steps = steps
+
+    def last_run_ms(self):
+        s = self.shape
+        return self.times.get((s["variant"], s["threads"], s["blocks"]), 1.0) * self.steps
+
+
+def test_autotune_single_picks_fastest_and_reports_variants(tmp_path, monkeypatch):
+    import types
+    monkeypatch.setenv("WCC_AUTOTUNE_CACHE", str(tmp_path / "c.json"))
+    fake_torch = types.SimpleNamespace(cuda=types.SimpleNamespace(
+        get_device_properties=lambda i: types.SimpleNamespace(multi_processor_count=256),
+        synchronize=lambda: None))
+    monkeypatch.setitem(__import__("sys").modules, "torch", fake_torch)
+    times = {(2, 256, 768): 0.5, (1, 128, 0): 0.7, (1, 256, 0): 0.8}
+    s = _FakeSolver(times, {"threads": 256, "blocks": 0, "variant": 1})
+    best = autotune.tune_single(s, None, 0.25, steps=10, threads=(128, 256), block_factors=(0, 3), variants=(0, 1, 2))
+    assert (best["variant"], best["threads"], best["blocks"]) == (2, 256, 768)
+    assert best["per_variant_ms"] == {0: 1.0, 1: 0.7, 2: 0.5}
+    assert s.get_launch() == {"threads": 256, "blocks": 768, "variant": 2}
+    # the library's own default is timed too and kept when nothing beats it
+    s2 = _FakeSolver({(1, 256, 0): 0.1}, {"threads": 256, "blocks": 0, "variant": 1})
+    b2 = autotune.tune_single(s2, None, 0.25, steps=10, threads=(128,), block_factors=(3,), variants=(0, 2))
+    assert (b2["variant"], b2["threads"], b2["blocks"]) == (1, 256, 0) and b2["ms_per_step"] == 0.1
+    cache = json.load(open(tmp_path / "c.json"))
+    assert cache["single/euler/P3/fp64/lim/N2^20"]["variant"] == 1
