@@ -163,3 +163,38 @@ def test_autotune_single_picks_fastest_and_reports_variants(tmp_path, monkeypatc
     assert (b2["variant"], b2["threads"], b2["blocks"]) == (1, 256, 0) and b2["ms_per_step"] == 0.1
     cache = json.load(open(tmp_path / "c.json"))
     assert cache["single/euler/P3/fp64/lim/N2^20"]["variant"] == 1
+
+
+def test_autotune_batch_tries_every_schedule(tmp_path, monkeypatch):
+    import types
+    monkeypatch.setenv("WCC_AUTOTUNE_CACHE", str(tmp_path / "c.json"))
+    fake_torch = types.SimpleNamespace(cuda=types.SimpleNamespace(
+        get_device_properties=lambda i: types.SimpleNamespace(multi_processor_count=256),
+        synchronize=lambda: None))
+    monkeypatch.setitem(__import__("sys").modules, "torch", fake_torch)
+
+    class FakeBatch:
+        B = 4096
+
+        class params:
+            precision = 1
+
+        def __init__(self):
+            self.sched, self.seen = None, set()
+
+        def set_schedule(self, threads, blocks, mode):
+            self.sched = (threads, blocks, mode)
+            self.seen.add(mode)
+
+        def run(self, steps, cfl):
+            self.steps = steps
+
+        def last_run_ms(self):
+            th, bl, mode = self.sched
+            return (1.0 - 0.05 * mode - (0.01 if bl == 1024 else 0.0)) * self.steps
+
+    bt = FakeBatch()
+    best = autotune.tune_batch(bt, [0.4] * 5, steps=8)
+    assert bt.seen == {1, 2, 3, 4, 5, 6}
+    assert (best["mode"], best["blocks"]) == (6, 1024) and bt.sched == (best["threads"], 1024, 6)
+    assert autotune.cached_batch(bt)["mode"] == 6
