@@ -256,9 +256,18 @@ class Solver:
         return ms.value
 
     def close(self):
+        """Destroy the context and release its device workspace (idempotent)."""
         if getattr(self, "h", None):
             load().wcc_destroy(self.h)
             self.h = None
+        self.workspace = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+        return False
 
     def __del__(self):
         try:
@@ -337,9 +346,18 @@ class Batch:
         return ms.value
 
     def close(self):
+        """Destroy the batch and release its device workspace (idempotent)."""
         if getattr(self, "h", None):
             load().wcc_batch_destroy(self.h)
             self.h = None
+        self.workspace = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+        return False
 
     def __del__(self):
         try:
@@ -440,9 +458,18 @@ class Solver2D:
         return ms.value
 
     def close(self) -> None:
+        """Destroy the context and release its device workspace (idempotent)."""
         if getattr(self, "h", None):
             load().wcc2d_destroy(self.h)
             self.h = None
+        self.workspace = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+        return False
 
     def __del__(self):
         try:

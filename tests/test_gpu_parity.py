@@ -364,3 +364,21 @@ def test_blowup_is_flagged_and_kept():
     with pytest.raises(binding.WccError) as e:
         s.advance(1e9, 0.3)
     assert e.value.code == binding.WCC_ENONFINITE
+
+
+def test_context_managers_release_the_workspace():
+    """`with` blocks destroy the contexts and drop their device workspaces."""
+    q0, kw = scalar_data("advection", 2, 64)
+    with binding.Solver("advection", 2, 64, "periodic", limiter=False, **kw) as s:
+        s.write(q0)
+        s.run(4, 0.25)
+        q, info = s.read()
+    assert s.h is None and s.workspace is None and info.half_steps == 4
+    s.close()                                  # idempotent
+    spec = inputs.batch_spec(3, 1, n_lo=40, n_hi=100)
+    with binding.Batch("euler", spec.P, spec.N, "transmissive", limiter=True) as bt:
+        bt.write(0, inputs.batch_instance(spec, 0))
+    assert bt.h is None and bt.workspace is None
+    with binding.Solver2D("burgers", 1, 8, 8, limiter=True) as s2:
+        pass
+    assert s2.h is None and s2.workspace is None
