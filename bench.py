@@ -179,7 +179,8 @@ def time_2d(args):
     unlimited (LCCS) and with the rotated characteristic limiter (WCCS); the
     first 2D Riemann problem of Section 5.3 with 1200 x 1200 intervals on
     [-1, 1]^2, transmissive edges, limited, P = 3.
-    Binary64, the library's default launch (row marching with prefetch).
+    Binary64; launch shape from the autotuner (row-marching variant, threads,
+    grid; --tune off: the library's default).
     Algorithmic bytes per launch: every old cell read once and every new cell
     written once, nc * ndof doubles each; `traffic` is the measured HBM bytes
     per launch from the committed counter record (null if it is stale)."""
@@ -194,11 +195,23 @@ def time_2d(args):
               lambda: inputs.isentropic_vortex(3, args.n2d_euler)),
              ("riemann2d_1_lim_P3", "euler", 3, args.n2d_riemann, True, (-1.0, 1.0, -1.0, 1.0), 0.25,
               lambda: inputs.riemann2d(1, 3, args.n2d_riemann))]
+    from paper_2104_04347_amd import autotune
     for name, eq, P, N, lim, dom, cfl, make in cases:
         q0 = make()
         bc = "transmissive" if name.startswith("riemann") else "periodic"
         s = binding.Solver2D(eq, P, N, N, limiter=lim, x_left=dom[0], x_right=dom[1], y_left=dom[2], y_right=dom[3],
                              bc=bc)
+        # launch shape: the library's default (row marching with prefetch, 256
+        # threads, device-filling grid), a cached autotuner result, or tune now
+        launch = {"variant": 2, "threads": 256, "blocks": 0, "source": "library default"}
+        if args.tune != "off":
+            c = autotune.cached_2d(s) if args.tune == "auto" else None
+            if c is None:
+                c = autotune.tune_2d(s, q0, cfl)
+                launch = {k: c[k] for k in ("variant", "threads", "blocks")} | {"source": "autotuned"}
+            else:
+                launch = {k: c[k] for k in ("variant", "threads", "blocks")} | {"source": "autotune cache"}
+            s.set_launch(launch["threads"], launch["blocks"], launch["variant"])
         s.write(q0)
         s.run(args.warmup2d, cfl)
         torch.cuda.synchronize()
@@ -214,11 +227,16 @@ def time_2d(args):
         cells = N * N if bc == "periodic" else 0.5 * ((N + 1) ** 2 + N * N)
         dofs = cells * nc * nd * args.steps2d
         bpl = 2.0 * cells * nc * nd * 8
-        kernel = f"k2d_half_step_rows<{eq},P={P},{'limiter' if lim else 'no limiter'},prefetch>"
+        kernel = (f"k2d_half_step_rows<{eq},P={P},{'limiter' if lim else 'no limiter'},"
+                  f"{'prefetch' if launch['variant'] == 2 else 'no prefetch'}>")
+        # the counter record belongs to the kernel, the mesh and the launch
+        # grid (the grid sets how many priming rows are re-read)
+        rec_key = (kernel + ("" if bc == "periodic" else ",transmissive") +
+                   f",grid={launch['threads']}x{launch['blocks']}")
         e = {"value": dofs / wall, "unit": "cell-DOF updates/s", "N": N, "P": P, "limiter": lim, "bc": bc,
-             "cfl": cfl, "half_steps": args.steps2d, "kernel": kernel, "launch_us": launch_s * 1e6,
+             "cfl": cfl, "half_steps": args.steps2d, "kernel": kernel, "launch": launch, "launch_us": launch_s * 1e6,
              "bytes_per_launch": bpl, "hbm_frac": bpl / launch_s / HBM_PEAK,
-             "traffic": measured_traffic(kernel + ("" if bc == "periodic" else ",transmissive"), N, "2d"),
+             "traffic": measured_traffic(rec_key, N, "2d"), "traffic_key": rec_key,
              "valid": bool((info.flags & 3) == 0)}
         s.close()
         if not args.no_cpu:

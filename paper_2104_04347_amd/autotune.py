@@ -7,6 +7,7 @@ single-instance runs in both schedules), so the tuner only measures time:
 * single instance: kernel variant (prefetch, staged line-aligned stores,
   both, neither) x threads per block (64..256) x blocks per launch
   (multiples of the device's resident-block capacity);
+* 2D: row-marching variant x threads x blocks per launch;
 * batched: schedule mode (fused: one launch per half-step switching on the
   degree per tile; grouped: one launch per degree, in sequence or as
   parallel graph branches; each with or without staged stores) x threads x
@@ -155,5 +156,49 @@ def tune_batch(batch: "binding.Batch", cfl_by_P, steps: int = 24, modes=(1, 2, 3
     c[key_batch(batch)] = {
         k: best[k] for k in ("mode", "threads", "blocks", "ms_per_step")}
     _save_cache(c)
+    best["tried"] = results
+    return best
+
+
+def key_2d(solver: "binding.Solver2D") -> str:
+    bx, by = solver.bcs
+    return (f"2d/{solver.equation}/P{solver.P}/{'lim' if solver.params.limiter else 'nolim'}/"
+            f"{solver.Nx}x{solver.Ny}/{bx},{by}")
+
+
+def cached_2d(solver: "binding.Solver2D"):
+    """The cached launch shape for `solver`'s configuration, or None."""
+    return _load_cache().get(key_2d(solver))
+
+
+def tune_2d(solver: "binding.Solver2D", q0: np.ndarray, cfl: float, steps: int = 96, threads=(128, 256),
+            block_factors=(0, 0.5, 1, 2, 3, 4), variants=(1, 2), verbose: bool = False) -> dict:
+    """Time 2D launch shapes on `solver` (state q0): row-marching variant
+    (1 without, 2 with the next row prefetched) x threads per block x blocks
+    per launch (block factor x compute units; 0 = the library's default,
+    which fills the device at the kernel's occupancy).  Longer runs per wave
+    re-expand fewer priming rows, more waves hide more latency; the best
+    balance depends on the degree and the mesh, hence the measurement."""
+    import torch
+    cu = torch.cuda.get_device_properties(0).multi_processor_count
+    results = []
+    for var in variants:
+        for th in threads:
+            for bf in block_factors:
+                blocks = 0 if bf == 0 else max(1, int(round(bf * cu)))
+                solver.set_launch(th, blocks, var)
+                solver.write(q0)
+                solver.run(48, cfl)            # warm-up, builds the graphs of this shape
+                torch.cuda.synchronize()
+                solver.run(steps, cfl)
+                ms = solver.last_run_ms() / steps
+                results.append({"variant": var, "threads": th, "blocks": blocks, "ms_per_step": ms})
+                if verbose:
+                    print(f"  variant={var} threads={th:4d} blocks={blocks:6d}: {ms * 1e3:8.2f} us/half-step", flush=True)
+    best = min(results, key=lambda r: r["ms_per_step"])
+    c = _load_cache()
+    c[key_2d(solver)] = {k: best[k] for k in ("variant", "threads", "blocks", "ms_per_step")}
+    _save_cache(c)
+    solver.set_launch(best["threads"], best["blocks"], best["variant"])
     best["tried"] = results
     return best

@@ -198,3 +198,36 @@ def test_autotune_batch_tries_every_schedule(tmp_path, monkeypatch):
     assert bt.seen == {1, 2, 3, 4, 5, 6}
     assert (best["mode"], best["blocks"]) == (6, 1024) and bt.sched == (best["threads"], 1024, 6)
     assert autotune.cached_batch(bt)["mode"] == 6
+
+
+def test_autotune_2d_keys_and_choice(tmp_path, monkeypatch):
+    import types
+    monkeypatch.setenv("WCC_AUTOTUNE_CACHE", str(tmp_path / "c.json"))
+    fake_torch = types.SimpleNamespace(cuda=types.SimpleNamespace(
+        get_device_properties=lambda i: types.SimpleNamespace(multi_processor_count=256),
+        synchronize=lambda: None))
+    monkeypatch.setitem(__import__("sys").modules, "torch", fake_torch)
+
+    class Fake2D:
+        equation, P, Nx, Ny, bcs = "burgers", 3, 2048, 2048, ("periodic", "periodic")
+
+        class params:
+            limiter = 1
+
+        def set_launch(self, threads, blocks, variant):
+            self.shape = (variant, threads, blocks)
+
+        def write(self, q0):
+            pass
+
+        def run(self, steps, cfl):
+            self.steps = steps
+
+        def last_run_ms(self):
+            return (0.18 if self.shape == (2, 256, 256) else 0.2) * self.steps
+
+    s = Fake2D()
+    best = autotune.tune_2d(s, None, 0.25, steps=8)
+    assert (best["variant"], best["threads"], best["blocks"]) == (2, 256, 256) and s.shape == (2, 256, 256)
+    assert autotune.key_2d(s) == "2d/burgers/P3/lim/2048x2048/periodic,periodic"
+    assert autotune.cached_2d(s)["blocks"] == 256
