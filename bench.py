@@ -231,8 +231,9 @@ def time_2d(args):
                   f"{'prefetch' if launch['variant'] == 2 else 'no prefetch'}>")
         # the counter record belongs to the kernel, the mesh and the launch
         # grid (the grid sets how many priming rows are re-read)
+        eff = s.get_launch()                   # the grid actually launched (0 resolved)
         rec_key = (kernel + ("" if bc == "periodic" else ",transmissive") +
-                   f",grid={launch['threads']}x{launch['blocks']}")
+                   f",grid={eff['threads']}x{eff['blocks']}")
         e = {"value": dofs / wall, "unit": "cell-DOF updates/s", "N": N, "P": P, "limiter": lim, "bc": bc,
              "cfl": cfl, "half_steps": args.steps2d, "kernel": kernel, "launch": launch, "launch_us": launch_s * 1e6,
              "bytes_per_launch": bpl, "hbm_frac": bpl / launch_s / HBM_PEAK,

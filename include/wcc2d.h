@@ -133,6 +133,12 @@ int wcc2d_totals(wcc2d_ctx* c, double* per_component);
  * the current one).  Results do not depend on it.  Errors: WCC_EINVAL. */
 int wcc2d_set_launch(wcc2d_ctx* c, int threads_per_block, int blocks, int variant);
 
+/* The launch shape the next half-step uses: threads per block, the
+ * effective number of blocks (the resident capacity resolved for the
+ * current mesh when wcc2d_set_launch was given 0) and the variant.
+ * Errors: WCC_EINVAL for a NULL argument. */
+int wcc2d_get_launch(wcc2d_ctx* c, int* threads_per_block, int* blocks, int* variant);
+
 /* Milliseconds between the HIP events around the last wcc2d_run. */
 int wcc2d_last_run_ms(wcc2d_ctx* c, double* ms);
 

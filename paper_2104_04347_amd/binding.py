@@ -107,6 +107,7 @@ SIGNATURES = {
     "wcc2d_advance": ([_vp, _c.c_double, _c.c_double, _i64, _c.POINTER(_i64)], _c.c_int),
     "wcc2d_read_dofs": ([_vp, _dp, _i64, _c.POINTER(wcc2d_state_info)], _c.c_int),
     "wcc2d_set_launch": ([_vp, _c.c_int, _c.c_int, _c.c_int], _c.c_int),
+    "wcc2d_get_launch": ([_vp, _c.POINTER(_c.c_int), _c.POINTER(_c.c_int), _c.POINTER(_c.c_int)], _c.c_int),
     "wcc2d_totals": ([_vp, _dp], _c.c_int),
     "wcc2d_last_run_ms": ([_vp, _dp], _c.c_int),
     "wcc2d_last_error": ([_vp], _c.c_char_p),
@@ -451,6 +452,13 @@ class Solver2D:
     def set_launch(self, threads: int = 0, blocks: int = 0, variant: int = -1) -> None:
         _check(load().wcc2d_set_launch(self.h, int(threads), int(blocks), int(variant)), "wcc2d_set_launch", self.h,
                two_d=True)
+
+    def get_launch(self) -> dict:
+        """The launch shape of the next half-step, with the effective block count."""
+        t, b, v = _c.c_int(), _c.c_int(), _c.c_int()
+        _check(load().wcc2d_get_launch(self.h, _c.byref(t), _c.byref(b), _c.byref(v)), "wcc2d_get_launch", self.h,
+               two_d=True)
+        return {"threads": t.value, "blocks": b.value, "variant": v.value}
 
     def last_run_ms(self) -> float:
         ms = ctypes.c_double()

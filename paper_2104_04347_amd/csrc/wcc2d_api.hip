@@ -464,6 +464,14 @@ int wcc2d_totals(wcc2d_ctx* c, double* per_component) {
   return WCC_OK;
 }
 
+int wcc2d_get_launch(wcc2d_ctx* c, int* threads_per_block, int* blocks, int* variant) {
+  if (!c || !threads_per_block || !blocks || !variant) return WCC_EINVAL;
+  *threads_per_block = c->threads;
+  *blocks = blocks_for(c, parity_now(c));
+  *variant = c->variant;
+  return WCC_OK;
+}
+
 int wcc2d_set_launch(wcc2d_ctx* c, int threads_per_block, int blocks, int variant) {
   if (!c) return WCC_EINVAL;
   if (variant < -1 || variant > 2) return fail2(c, WCC_EINVAL, "variant must be -1 (keep), 0, 1 or 2");

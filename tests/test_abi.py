@@ -156,4 +156,11 @@ def test_2d_create_validates():
     assert lib.wcc2d_set_launch(h, 100, 0, -1) == binding.WCC_EINVAL
     assert lib.wcc2d_set_launch(h, 0, 0, 3) == binding.WCC_EINVAL
     assert lib.wcc2d_set_launch(h, 128, 0, 0) == 0
+    t, b, v = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    assert lib.wcc2d_get_launch(h, ctypes.byref(t), ctypes.byref(b), ctypes.byref(v)) == 0
+    assert t.value == 128 and v.value == 0 and b.value >= 1          # blocks resolved, never 0
+    assert lib.wcc2d_set_launch(h, 256, 300, 2) == 0
+    assert lib.wcc2d_get_launch(h, ctypes.byref(t), ctypes.byref(b), ctypes.byref(v)) == 0
+    assert (t.value, b.value, v.value) == (256, 300, 2)
+    assert lib.wcc2d_get_launch(h, None, ctypes.byref(b), ctypes.byref(v)) == binding.WCC_EINVAL
     lib.wcc2d_destroy(h)
