@@ -20,6 +20,7 @@ from oracle import build as obuild
 from paper_2104_04347_amd import inputs
 
 from test_oracle_linear import _mat, oracle_matrices
+import test_oracle_boundary_speed as tbs
 
 import json
 
@@ -48,6 +49,17 @@ MUTANTS = {
     "weight normalisation term": ("R inv = R(1.0) / ((wh0 + wh1) + wh2);", "R inv = R(1.0) / (wh0 + wh1);"),
     "high-order weight +1 dropped": ("wh0 = fmaR(r0, r0, R(1.0));", "wh0 = r0 * r0;"),
     "tau from d1": ("R tau = d[P] * d[P];", "R tau = d[1] * d[1];"),
+    "Dirichlet side swap": ("const double* st = side == 0 ? pb.left_state : pb.right_state;",
+                            "const double* st = side == 0 ? pb.right_state : pb.left_state;"),
+    "Dirichlet ghost keeps derivatives": (
+        "q[c][k] = (k == 0) ? st[c] : 0.0;",
+        "q[c][k] = (k == 0) ? st[c] : old_dofs[((int64_t)c * (P + 1) + k) * n_old + (side == 0 ? 0 : n_old - 1)];"),
+    "speed without |u| (new cells)": ("speed = absR(eu) + ec;", "speed = eu + ec;"),
+    "speed without |u| (state)": ("return absR(u) + c;", "return u + c;"),
+    "Burgers speed without |u|": ("if (pb.equation == EQ_BURGERS) return absR(abar[0]);",
+                                  "if (pb.equation == EQ_BURGERS) return abar[0];"),
+    "advection speed without |a|": ("if (pb.equation == EQ_ADVECTION) return absR(R(pb.a));",
+                                    "if (pb.equation == EQ_ADVECTION) return R(pb.a);"),
 }
 
 
@@ -144,7 +156,16 @@ def quick_pins() -> list:
                     return False
         return True
 
+    def dirichlet_ends():
+        return (dirichlet_appendix() and tbs.dirichlet_contact_ends_kept(2, True)
+                and tbs.dirichlet_inflow_errors(3, Ns=(100,))[0] < 1e-4)
+
+    def dirichlet_appendix():
+        return all(tbs.dirichlet_end_cells_match_appendix(P, 0.2371) < 4e-15 for P in (1, 2, 3))
+
     check("appendix A", appendix)
+    check("Dirichlet ghosts", dirichlet_ends)
+    check("wave speed", tbs.wave_speed_time_steps_ok)
     check("limiter brute force", limiter_brute)
     check("table 1", table1)
     check("gamma=3 order", gamma3)
