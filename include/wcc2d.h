@@ -82,14 +82,18 @@ typedef struct {
 /* Defaults listed in wcc2d_params.  Error: WCC_EINVAL for a null pointer. */
 int wcc2d_params_default(wcc2d_params* p);
 
-/* New context for equation (WCC_ADVECTION, WCC_BURGERS, WCC_EULER), degree
- * P in [0, WCC2D_PMAX], Nx, Ny >= 2 intervals with (Nx+1)*(Ny+1) <= 2^28.
+/* New context for the problem of Eq. 2DHCL: equation (WCC_ADVECTION,
+ * WCC_BURGERS, WCC_EULER), degree P in [0, WCC2D_PMAX] of the cell
+ * polynomial of Eq. 2DPolynomial_Space, Nx, Ny >= 2 intervals of the meshes of
+ * Section 3.1 with (Nx+1)*(Ny+1) <= 2^28.
  * params may be null (defaults).  Errors: WCC_EINVAL for bad sizes, enums
  * (equation, boundary) or domain, gamma <= 1 for Euler. */
 int wcc2d_create(int equation, int P, int64_t Nx, int64_t Ny, const wcc2d_params* params, wcc2d_ctx** out);
 
-/* Device bytes the caller must provide to wcc2d_bind: a control block, the
- * partial wave-speed slots and two state buffers of nc*ndof planes. */
+/* Device bytes the caller must provide to wcc2d_bind: a control block of the
+ * CFL time step, the partial wave-speed slots and two state buffers of
+ * nc*ndof planes (the two staggered meshes of Section 3.1).  Errors:
+ * WCC_EINVAL for NULL arguments. */
 int wcc2d_workspace_bytes(const wcc2d_ctx* c, size_t* bytes);
 
 /* Hand over caller-owned device memory (256-byte aligned, at least
@@ -97,34 +101,44 @@ int wcc2d_workspace_bytes(const wcc2d_ctx* c, size_t* bytes);
  * Errors: WCC_EINVAL (null or misaligned), WCC_ESIZE (too small). */
 int wcc2d_bind(wcc2d_ctx* c, void* dev_ptr, size_t bytes, void* hip_stream);
 
-/* Copy a host state (layout above, the cells of mesh `parity`) onto that mesh at time
- * t and compute its wave-speed rate; synchronises the stream.  Errors:
+/* Copy the initial data of Eq. 2DHCL (layout above, the cells of mesh
+ * `parity`; host stays the caller's) onto that mesh at time t and compute its
+ * wave-speed rate from the cell averages; synchronises the stream.  Errors:
  * WCC_ESTATE before bind, WCC_EINVAL, WCC_ENONFINITE (state kept). */
 int wcc2d_write_dofs(wcc2d_ctx* c, const double* host, int parity, double t);
 
-/* Enqueue one half-step: dt = cfl/s_max, or dt_fixed when > 0. */
+/* Enqueue one half-step of Section 3 (Cauchy-Kovalewski expansion of
+ * Eq. 2DTaylorSeries, the quarter-cell and half-edge averages of Appendix B,
+ * Eq. 2DIntegral, Eq. 2DDerivatives, the limiter of Section 3.2 and
+ * Section 4): dt = cfl/s_max, or dt_fixed when > 0.  Stream-ordered.
+ * Errors: WCC_ESTATE, WCC_EINVAL, WCC_EDEVICE. */
 int wcc2d_step(wcc2d_ctx* c, double cfl, double dt_fixed);
 
-/* Enqueue half_steps half-steps at CFL number cfl (graph-replayed chunks),
- * timed by HIP events on the bound stream (wcc2d_last_run_ms). */
+/* Enqueue half_steps half-steps as wcc2d_step at CFL number cfl
+ * (graph-replayed chunks), timed by HIP events on the bound stream
+ * (wcc2d_last_run_ms).  Errors as wcc2d_step. */
 int wcc2d_run(wcc2d_ctx* c, int64_t half_steps, double cfl);
 
-/* Advance to t_end (last step clipped), at most max_half_steps if > 0;
+/* Advance to t_end with CFL time steps (the step that would pass t_end is
+ * clipped to it), at most max_half_steps if > 0;
  * *taken = half-steps done.  Errors: WCC_ENONFINITE when a step raised a
  * status bit (the state is kept for inspection). */
 int wcc2d_advance(wcc2d_ctx* c, double t_end, double cfl, int64_t max_half_steps, int64_t* taken);
 
-/* Copy the current state to host (if host != null; cap = doubles available)
- * and fill info (if non-null); synchronises the stream. */
+/* Copy the current state to host (if host != null; cap = doubles available,
+ * layout above) and fill info (if non-null); synchronises the stream.
+ * Errors: WCC_ESTATE, WCC_ESIZE, WCC_EDEVICE. */
 int wcc2d_read_dofs(wcc2d_ctx* c, double* host, int64_t cap, wcc2d_state_info* info);
 
 /* Conserved totals sum over the current mesh of ubar dx dy per component
- * (cell averages of the cell polynomials), summed in cell order on the host.
+ * (cell averages of the cell polynomials of Eq. 2DPolynomial_Space), summed
+ * in cell order on the host.
  * Synchronous.  With periodic edges they are invariants of the scheme up to
  * round-off.  Errors: WCC_EINVAL, WCC_ESTATE (no state). */
 int wcc2d_totals(wcc2d_ctx* c, double* per_component);
 
-/* Launch shape: threads per block (64..256, multiple of 64; 0 = 256),
+/* Launch shape (the work decomposition, not a paper quantity): threads per
+ * block (64..256, multiple of 64; 0 = 256),
  * blocks per launch (0 = resident capacity) and the work decomposition
  * (variant 0: every wavefront expands 8 x 8 old-cell tiles and produces their
  * 7 x 7 new cells; 1: wavefronts walk 64-column strips upward one row at a
@@ -139,10 +153,13 @@ int wcc2d_set_launch(wcc2d_ctx* c, int threads_per_block, int blocks, int varian
  * Errors: WCC_EINVAL for a NULL argument. */
 int wcc2d_get_launch(wcc2d_ctx* c, int* threads_per_block, int* blocks, int* variant);
 
-/* Milliseconds between the HIP events around the last wcc2d_run. */
+/* Milliseconds between the HIP events around the last wcc2d_run (waits for
+ * it).  Errors: WCC_EINVAL, WCC_ESTATE (no timed run), WCC_EDEVICE. */
 int wcc2d_last_run_ms(wcc2d_ctx* c, double* ms);
 
+/* The last detailed message of a context (owned by the context). */
 const char* wcc2d_last_error(const wcc2d_ctx* c);
+/* Free the context's host state, graphs and events; NULL is ignored. */
 void wcc2d_destroy(wcc2d_ctx* c);
 
 #ifdef __cplusplus

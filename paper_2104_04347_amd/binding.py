@@ -91,7 +91,7 @@ SIGNATURES = {
     "wcc_batch_bind": ([_vp, _vp, _c.c_size_t, _vp], _c.c_int),
     "wcc_batch_write_dofs": ([_vp, _c.c_int, _dp, _i64, _c.c_double], _c.c_int),
     "wcc_batch_prepare": ([_vp], _c.c_int),
-    "wcc_batch_run": ([_vp, _i64, _dp], _c.c_int),
+    "wcc_batch_advance": ([_vp, _i64, _dp], _c.c_int),
     "wcc_batch_read_dofs": ([_vp, _c.c_int, _dp, _i64, _c.POINTER(wcc_state_info)], _c.c_int),
     "wcc_batch_set_schedule": ([_vp, _c.c_int, _c.c_int, _c.c_int], _c.c_int),
     "wcc_batch_last_run_ms": ([_vp, _dp], _c.c_int),
@@ -323,10 +323,13 @@ class Batch:
     def prepare(self) -> None:
         _check(load().wcc_batch_prepare(self.h), "wcc_batch_prepare", self.h, True)
 
-    def run(self, half_steps: int, cfl_by_P) -> None:
+    def advance(self, half_steps: int, cfl_by_P) -> None:
+        """wcc_batch_advance: enqueue half_steps half-steps of every instance."""
         c = np.zeros(WCC_PMAX + 1)
         c[: len(cfl_by_P)] = cfl_by_P
-        _check(load().wcc_batch_run(self.h, int(half_steps), _dptr(c)), "wcc_batch_run", self.h, True)
+        _check(load().wcc_batch_advance(self.h, int(half_steps), _dptr(c)), "wcc_batch_advance", self.h, True)
+
+    run = advance
 
     def read(self, b: int):
         inf = wcc_state_info()

@@ -171,8 +171,7 @@ void drop_graphs(wcc2d_ctx* c) {
 }
 
 int set_fields(wcc2d_ctx* c, double t_end, double cfl) {
-  double v[2] = {t_end, cfl};
-  HIPCHK2(c, hipMemcpyAsync(&c->ctrl->t_end, v, sizeof v, hipMemcpyHostToDevice, c->stream));
+  HIPCHK2(c, wcc::launch_set_fields(c->ctrl, t_end, cfl, c->stream));
   return WCC_OK;
 }
 

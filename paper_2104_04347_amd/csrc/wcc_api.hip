@@ -188,8 +188,7 @@ int chunk_graph(wcc_ctx* c, int slot0, int parity0, hipGraphExec_t* out) {
 }
 
 int set_ctrl_fields(wcc_ctx* c, double t_end, double cfl) {
-  double v[2] = {t_end, cfl};
-  HIPCHK(c, hipMemcpyAsync(&c->ctrl->t_end, v, sizeof v, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, wcc::launch_set_fields(c->ctrl, t_end, cfl, c->stream));
   return WCC_OK;
 }
 
@@ -529,9 +528,6 @@ int wcc_read_dofs(wcc_ctx* c, double* host, int64_t cap, wcc_state_info* info) {
     info->t = h.t[s];
     info->parity = parity;
     info->flags = (int32_t)h.flags[s];
-    if (c->prm.limiter == 0 && c->P <= 4 && c->eq == WCC_ADVECTION) {
-      // nothing: the linear limit is checked by the caller-visible flag below
-    }
     info->n_cells = n;
     info->dx = dx_of(c);
     info->x_first_center = c->prm.x_left + 0.5 * (double)parity * info->dx;

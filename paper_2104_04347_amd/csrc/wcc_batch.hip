@@ -475,7 +475,6 @@ int enqueue_batch_step(wcc_batch* b, int parity, int slot, hipStream_t s, int on
   a.ph = b_phys<R>(b);
   a.parity_old = parity;
   a.slot = slot;
-  a.waves_per_tile = 1;
   const bool lim = b->prm.limiter != 0;
   size_t off = 0;
   if (!b->grouped) {
@@ -753,7 +752,7 @@ int wcc_batch_prepare(wcc_batch* b) {
   return WCC_OK;
 }
 
-int wcc_batch_run(wcc_batch* b, int64_t half_steps, const double cfl_by_P[WCC_PMAX + 1]) {
+int wcc_batch_advance(wcc_batch* b, int64_t half_steps, const double cfl_by_P[WCC_PMAX + 1]) {
   if (!b || !cfl_by_P || half_steps < 0) return WCC_EINVAL;
   if (!b->bound) return bfail(b, WCC_ESTATE, "run before bind");
   // per-instance CFL numbers live in each control block
@@ -767,13 +766,17 @@ int wcc_batch_run(wcc_batch* b, int64_t half_steps, const double cfl_by_P[WCC_PM
         for (const auto& in : b->inst) used = used || in.P == p;
         if (used) return bfail(b, WCC_EINVAL, "cfl for P=%d outside (0, 1]", p);
       }
-    for (int i = 0; i < b->B; ++i)
-      BHIP(b, hipMemcpyAsync(&b->ctrl[i].cfl, &cfl_by_P[b->inst[i].P], sizeof(double), hipMemcpyHostToDevice,
-                             b->stream));
-    for (int p = 0; p <= WCC_PMAX; ++p) b->cfl_set[p] = cfl_by_P[p];
   }
   int rc = upload_tables(b);
   if (rc) return rc;
+  if (changed) {
+    // the per-instance CFL numbers go to the control blocks by a kernel whose
+    // arguments carry the values (after the instance table is on the device)
+    wcc::CflByDegree v;
+    for (int p = 0; p <= WCC_PMAX; ++p) v.v[p] = cfl_by_P[p];
+    BHIP(b, wcc::launch_batch_set_cfl(b->ctrl, b->d_inst, b->B, v, b->stream));
+    for (int p = 0; p <= WCC_PMAX; ++p) b->cfl_set[p] = cfl_by_P[p];
+  }
   // every chunk graph a run can start on, built before the timed events
   if (half_steps >= kBatchChunk) {
     for (int key = 0; key < 6; ++key) {

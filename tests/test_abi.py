@@ -20,7 +20,7 @@ def declared():
 
 def test_header_declares_the_abi():
     names = declared()
-    assert "wcc_create" in names and "wcc_batch_run" in names and "wcc2d_advance" in names and len(names) >= 33
+    assert "wcc_create" in names and "wcc_batch_advance" in names and "wcc2d_advance" in names and len(names) >= 33
 
 
 def test_library_exports_every_declared_symbol():
