@@ -30,7 +30,17 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK = 8.0e12          # bytes/s, MI355X HBM3E
 FP64_VALU_PEAK = 78.6e12   # flop/s, fma counted as 2
-FP32_VALU_PEAK = 157.3e12  # flop/s (packed / dual-issue)
+# binary32 without packed instructions (this build compiles with the packed
+# FP32 operations disabled): one 64-lane instruction per 4 cycles per SIMD,
+# the binary64 rate
+FP32_VALU_PEAK = 78.6e12
+# VALU issue: 256 CUs x 4 SIMDs, one 64-lane (wave) VALU instruction per 4
+# cycles per SIMD at the 2.4 GHz peak engine clock
+N_SIMD = 1024
+CLOCK_HZ = 2.4e9
+CYCLES_PER_VALU_INST = 4
+VALU_ISSUE_PEAK = N_SIMD * CLOCK_HZ / CYCLES_PER_VALU_INST   # wave-instructions/s
+MALL_BYTES = 256 * 1048576  # Infinity Cache (MALL) of the MI355X
 CFL_BY_P = [0.4, 0.4, 0.3, 0.25, 0.25]
 
 
@@ -49,6 +59,34 @@ def measured_traffic(kernel: str, N: int, sources: str = "1d"):
     if not e or e.get("source_sha256") != kernel_source_hash(sources) or e.get("N") != N:
         return None
     return e["fetch_bytes"] + e["write_bytes"]
+
+
+def valu_insts(kernel: str, N: int, sources: str = "1d"):
+    """Mean SQ_INSTS_VALU (64-lane VALU instructions) per launch from the
+    committed counter record, or None when it is for another build or size."""
+    path = os.path.join(ROOT, "profiles", "valu_insts.json")
+    try:
+        with open(path) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    from paper_2104_04347_amd.profsum import kernel_source_hash
+    e = rec.get(kernel)
+    if not e or e.get("source_sha256") != kernel_source_hash(sources) or e.get("N") != N:
+        return None
+    return e["sq_insts_valu"]
+
+
+def issue_roof(kernel: str, N: int, launch_s: float, sources: str = "1d"):
+    """VALU issue roof: the launch's VALU instructions at one per 4 cycles on
+    every SIMD at the peak clock, against the measured launch time."""
+    insts = valu_insts(kernel, N, sources)
+    if insts is None:
+        return None
+    t_issue = insts / VALU_ISSUE_PEAK
+    return {"bound": "alu", "unit": "Ginst/s", "achieved": round(insts / launch_s / 1e9, 1),
+            "peak": round(VALU_ISSUE_PEAK / 1e9, 1), "frac": round(t_issue / launch_s, 4),
+            "valu_insts_per_launch": insts, "issue_floor_us": round(t_issue * 1e6, 2)}
 
 
 def flop_counts():
@@ -92,7 +130,7 @@ def launch_shape_single(args, s, q0, cfl=None, **tune_kw) -> dict:
             "best_us_per_variant": {str(v): round(ms * 1e3, 2) for v, ms in best["per_variant_ms"].items()}}
 
 
-def time_single(args, precision: str, q0):
+def time_single(args, precision: str, q0, keep_state: bool = False):
     import torch
     from paper_2104_04347_amd import binding
     P, N = args.P, args.N
@@ -119,8 +157,20 @@ def time_single(args, precision: str, q0):
     dofs = cells * 3 * (P + 1)
     out = dict(value=dofs / wall, wall_s=wall, event_ms=ev_ms, lib_event_ms=lib_ms, flags=int(info.flags),
                ok=ok, t=info.t, half_steps=int(info.half_steps), launch=shape)
+    if keep_state:
+        out["q"] = s.read()[0]
     s.close()
     return out
+
+
+def mixed_vs_fp64(q_mixed, q_fp64) -> dict:
+    """Point-value L1 (mean) and Linf distance of the FP32-mixed result from
+    the binary64 result (itself bit for bit the FP64 oracle's), per
+    component, relative to the largest |value| of the binary64 field."""
+    d = q_mixed[:, 0] - q_fp64[:, 0]
+    scale = np.abs(q_fp64[:, 0]).max(axis=1)
+    return {"L1_rel": [float(np.abs(d[c]).mean() / scale[c]) for c in range(d.shape[0])],
+            "Linf_rel": [float(np.abs(d[c]).max() / scale[c]) for c in range(d.shape[0])]}
 
 
 def time_batch(args):
@@ -164,12 +214,37 @@ def time_batch(args):
     # algorithmic bytes of one half-step of every instance (old + new cells)
     bph = sum(bytes_per_launch(int(n), int(p), 3, "fp32_mixed") for n, p in zip(spec.N, spec.P))
     gbs = bph * args.batch_steps / (ms / 1e3) / 1e9
+    out = dict(value=spec.P.size / wall, unit="solves/s", instances=int(spec.P.size),
+               half_steps_each=args.batch_steps, wall_s=wall, event_ms=ms, cell_dof_per_s=dofs / wall,
+               total_cells=int(np.sum(spec.N)), cells_per_s=cells / wall, bytes_per_half_step=bph,
+               gbs=round(gbs, 1), hbm_frac=round(gbs * 1e9 / HBM_PEAK, 4), flags=int(flags),
+               schedule=sched or "default")
+    # the single-launch form: every instance's half-step in ONE persistent
+    # launch (fused schedules 1 and 3: direct / staged stores), timed the same way
+    fused = {}
+    for mode in args.batch_fused_modes:
+        load_instances(again=True)
+        bt.set_schedule(sched[0] if sched else 256, 0, mode)
+        bt.run(args.batch_warmup, CFL_BY_P)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        bt.run(args.batch_steps, CFL_BY_P)
+        torch.cuda.synchronize()
+        w = time.perf_counter() - t0
+        m = bt.last_run_ms()
+        g = bph * args.batch_steps / (m / 1e3) / 1e9
+        fl = 0
+        for b in range(0, spec.P.size, max(1, spec.P.size // 64)):
+            fl |= bt.read(b)[1].flags & 3
+        fused[str(mode)] = {"value": spec.P.size / w, "unit": "solves/s", "event_ms": m,
+                            "launches_per_half_step": 1, "gbs": round(g, 1),
+                            "hbm_frac": round(g * 1e9 / HBM_PEAK, 4), "flags": int(fl)}
+        print(f"[bench] batched, one launch per half-step (mode {mode}): {spec.P.size / w:.1f} solves/s",
+              file=sys.stderr, flush=True)
+    if fused:
+        out["one_launch_form"] = fused
     bt.close()
-    return dict(value=spec.P.size / wall, unit="solves/s", instances=int(spec.P.size),
-                half_steps_each=args.batch_steps, wall_s=wall, event_ms=ms, cell_dof_per_s=dofs / wall,
-                total_cells=int(np.sum(spec.N)), cells_per_s=cells / wall, bytes_per_half_step=bph,
-                gbs=round(gbs, 1), hbm_frac=round(gbs * 1e9 / HBM_PEAK, 4), flags=int(flags),
-                schedule=sched or "default")
+    return out
 
 
 def time_2d(args):
@@ -311,40 +386,58 @@ def time_large(args):
         q, info = s.read()
         finals[prec] = q[:, 0].copy()
         abs0 = np.abs(q0[:, 0]).sum(axis=1) * (1.0 / N)   # scale of the totals
+        launch_s = s.last_run_ms() / 1e3 / args.large_steps
+        # periodic: N old + N new cells per launch
+        bpl = 2.0 * N * 3 * (8 + P * (8 if prec == "fp64" else 4))
         out[prec] = {"value": N * 3 * (P + 1) * args.large_steps / wall, "unit": "cell-DOF updates/s",
                      "wall_s": wall, "ms_per_step": s.last_run_ms() / args.large_steps, "t": info.t,
-                     "launch": shape,
+                     "launch": shape, "launch_us": round(launch_s * 1e6, 2), "bytes_per_launch": bpl,
+                     "gbs": round(bpl / launch_s / 1e9, 1), "frac": round(bpl / launch_s / HBM_PEAK, 4),
+                     "mall_resident": bool(bpl <= MALL_BYTES),
                      "flags": int(info.flags),
                      "drift_rel": [float(abs(a - b) / c) for a, b, c in zip(tot, tot0, abs0)]}
         del q
         s.close()
     if not args.no_cpu and args.large_cpu_steps > 0:
         import oracle
+        from oracle import build as obuild
         pb = oracle.Problem("euler", P, N, bc="periodic", limiter=True)
-        t0 = time.perf_counter()
-        r = oracle.run(pb, q0, cfl=cfl, max_half_steps=args.large_cpu_steps)
-        wall = time.perf_counter() - t0
+        with oracle.use_library(obuild.LIB_OMP):
+            nt = oracle.threads()
+            t0 = time.perf_counter()
+            r = oracle.run(pb, q0, cfl=cfl, max_half_steps=args.large_cpu_steps)
+            wall = time.perf_counter() - t0
         out["cpu_baseline"] = {"value": N * 3 * (P + 1) * r.half_steps / wall, "unit": "cell-DOF updates/s",
-                               "cores": 1, "kind": "oracle",
-                               "sample": f"first {r.half_steps} half-steps of the large workload, FP64 oracle, "
-                                         f"single thread, {wall:.1f} s"}
+                               "cores": nt, "kind": "oracle",
+                               "sample": f"first {r.half_steps} half-steps of the large workload, FP64 oracle "
+                                         f"(OpenMP build, {nt} threads), {wall:.1f} s"}
     d = finals["fp32_mixed"] - finals["fp64"]
     scale = np.abs(finals["fp64"]).max(axis=1)
     out["mixed_vs_fp64_point_values"] = {"L1_rel": [float(np.abs(d[c]).mean() / scale[c]) for c in range(3)],
-                                         "Linf_rel": [float(np.abs(d[c]).max() / scale[c]) for c in range(3)]}
+                                         "Linf_rel": [float(np.abs(d[c]).max() / scale[c]) for c in range(3)],
+                                         "t_fp64": out["fp64"]["t"], "t_fp32_mixed": out["fp32_mixed"]["t"]}
     return out
 
 
 def cpu_baseline(args, q0):
-    """The FP64 oracle as it stands, single-threaded, on a bounded sample of
-    the same workload: the first `cpu_steps` half-steps of the full mesh."""
+    """The FP64 oracle as it stands on a bounded sample of the same workload
+    (the first half-steps of the full mesh): the OpenMP build of the same
+    source on all host threads (`value`), and the serial build on one thread."""
     import oracle
+    from oracle import build as obuild
     pb = oracle.Problem("euler", args.P, args.N, bc="transmissive", limiter=True)
-    t0 = time.perf_counter()
-    r = oracle.run(pb, q0, cfl=args.cfl, max_half_steps=args.cpu_steps)
-    wall = time.perf_counter() - t0
-    cells = cells_updated(args.N, "transmissive", 0, r.half_steps)
-    dofs = cells * 3 * (args.P + 1)
+
+    def timed(lib, steps):
+        with oracle.use_library(lib):
+            nt = oracle.threads()
+            t0 = time.perf_counter()
+            r = oracle.run(pb, q0, cfl=args.cfl, max_half_steps=steps)
+            wall = time.perf_counter() - t0
+        dofs = cells_updated(args.N, "transmissive", 0, r.half_steps) * 3 * (args.P + 1)
+        return dofs / wall, nt, r.half_steps, wall
+
+    v1, _, n1, w1 = timed(obuild.LIB, args.cpu_steps)
+    vm, nt, nm, wm = timed(obuild.LIB_OMP, args.cpu_omp_steps)
     cpu_model = ""
     try:
         for line in open("/proc/cpuinfo"):
@@ -353,9 +446,11 @@ def cpu_baseline(args, q0):
                 break
     except OSError:
         pass
-    return {"value": dofs / wall, "unit": "cell-DOF updates/s", "cores": 1, "kind": "oracle",
-            "sample": f"first {r.half_steps} half-steps of the full workload (N={args.N}, P={args.P}), "
-                      f"FP64 oracle, single thread, {wall:.1f} s",
+    return {"value": vm, "unit": "cell-DOF updates/s", "cores": nt, "kind": "oracle",
+            "sample": f"first {nm} half-steps of the full workload (N={args.N}, P={args.P}), FP64 oracle, "
+                      f"OpenMP build over cells, {nt} threads, {wm:.1f} s",
+            "single_thread": {"value": v1, "unit": "cell-DOF updates/s", "cores": 1, "kind": "oracle",
+                              "sample": f"first {n1} half-steps, serial build, {w1:.1f} s"},
             "cpu_model": cpu_model, "host_threads": os.cpu_count()}
 
 
@@ -375,8 +470,12 @@ def main():
     ap.add_argument("--batch-steps", type=int, default=100)
     ap.add_argument("--batch-warmup", type=int, default=24)
     ap.add_argument("--batch-schedule", default="", help="threads,blocks,mode for the batched kernels")
-    ap.add_argument("--cpu-steps", type=int, default=24)
-    ap.add_argument("--large-cpu-steps", type=int, default=5, help="oracle half-steps timed on the large workload")
+    ap.add_argument("--batch-fused-modes", default="1,3",
+                    help="also time these fused (one launch per half-step) batch schedules ('' for none)")
+    ap.add_argument("--cpu-steps", type=int, default=12, help="serial oracle half-steps timed")
+    ap.add_argument("--cpu-omp-steps", type=int, default=48, help="OpenMP oracle half-steps timed")
+    ap.add_argument("--large-cpu-steps", type=int, default=2,
+                    help="OpenMP oracle half-steps timed on the large workload")
     ap.add_argument("--no-2d", action="store_true", help="skip the 2D legs")
     ap.add_argument("--n2d", type=int, default=2048, help="2D Burgers mesh (n2d x n2d)")
     ap.add_argument("--n2d-euler", type=int, default=1024, help="2D Euler vortex mesh")
@@ -385,7 +484,7 @@ def main():
     ap.add_argument("--warmup2d", type=int, default=96)
     ap.add_argument("--seeds", default="0,1,2,3,4",
                     help="also time the FP64 and mixed legs on these seeds of the same workload ('' for none)")
-    ap.add_argument("--large", action="store_true", help="also run the large 16.7M-cell P=4 workload")
+    ap.add_argument("--no-large", action="store_true", help="skip the large 16.7M-cell P=4 workload")
     ap.add_argument("--large-N", type=int, default=1 << 24)
     ap.add_argument("--large-steps", type=int, default=10000)
     ap.add_argument("--large-variant", type=int, default=-1, choices=(-1, 0, 1, 2, 3),
@@ -395,6 +494,7 @@ def main():
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="also run 5 device-to-device copies of this many MiB (counter calibration)")
     args = ap.parse_args()
+    args.batch_fused_modes = [int(v) for v in args.batch_fused_modes.split(",") if v.strip()]
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: the library has no multi-GPU path; run with --gpus 1",
@@ -411,12 +511,15 @@ def main():
 
     q0, _ = inputs.euler_riemann(args.seed, args.P, args.N)
     print(f"[bench] workload ready: Euler P={args.P} N={args.N}", file=sys.stderr, flush=True)
-    r64 = time_single(args, "fp64", q0)
+    r64 = time_single(args, "fp64", q0, keep_state=not args.no_mixed)
     print(f"[bench] fp64: {r64['value']:.3e} DOF/s", file=sys.stderr, flush=True)
     rmx = None
     if not args.no_mixed:
-        rmx = time_single(args, "fp32_mixed", q0)
+        rmx = time_single(args, "fp32_mixed", q0, keep_state=True)
         print(f"[bench] fp32_mixed: {rmx['value']:.3e} DOF/s", file=sys.stderr, flush=True)
+        rmx["vs_fp64"] = mixed_vs_fp64(rmx.pop("q"), r64.pop("q"))
+        rmx["vs_fp64"].update(t_fp64=r64["t"], t_fp32_mixed=rmx["t"],
+                              half_steps=r64["half_steps"])
     seeds_out = {}
     for sd in [int(v) for v in args.seeds.split(",") if v.strip()]:
         if sd == args.seed:
@@ -443,7 +546,7 @@ def main():
             print(f"[bench] 2D legs failed: {exc}", file=sys.stderr, flush=True)
 
     rl = None
-    if args.large:
+    if not args.no_large:
         rl = time_large(args)
         print(f"[bench] large: mixed {rl['fp32_mixed']['value']:.3e} DOF/s, fp64 {rl['fp64']['value']:.3e} DOF/s",
               file=sys.stderr, flush=True)
@@ -471,24 +574,30 @@ def main():
                     tflops=flops / 1e12, alu_frac=flops / peak_alu, alu_peak=peak_alu)
 
     ro = roof(r64, "fp64")
-    # the counter record is per kernel variant (prefetch / staged stores)
+    # the counter records are per kernel variant (prefetch / staged stores)
     kernel_key = f"k_half_step<euler,P={args.P},limiter,f64,variant={r64['launch']['variant']}>"
-    bound_hbm = ro["hbm_frac"] >= ro["alu_frac"]
-    roofline = {
-        "bound": "hbm" if bound_hbm else "alu",
-        "achieved": round(ro["gbs"], 1) if bound_hbm else round(ro["tflops"], 3),
-        "peak": HBM_PEAK / 1e9 if bound_hbm else FP64_VALU_PEAK / 1e12,
-        "unit": "GB/s" if bound_hbm else "TFLOP/s",
-        "frac": round(ro["hbm_frac"] if bound_hbm else ro["alu_frac"], 4),
-        "traffic": measured_traffic(kernel_key, args.N),
-        "kernel": kernel_key,
-        "launch_us": round(ro["launch_us"], 2),
-        "bytes_per_launch": ro["bytes_per_launch"],
-        "other_roof": ({"bound": "alu", "achieved": round(ro["tflops"], 3), "unit": "TFLOP/s",
-                        "peak": FP64_VALU_PEAK / 1e12, "frac": round(ro["alu_frac"], 4)} if bound_hbm else
-                       {"bound": "hbm", "achieved": round(ro["gbs"], 1), "unit": "GB/s",
-                        "peak": HBM_PEAK / 1e9, "frac": round(ro["hbm_frac"], 4)}),
-    }
+    launch_s = ro["launch_us"] / 1e6
+    issue = issue_roof(kernel_key, args.N, launch_s)
+    # the binding roof is the one with the longer floor: algorithmic bytes at
+    # the HBM peak, or the measured VALU instructions at the issue peak
+    t_hbm = ro["bytes_per_launch"] / HBM_PEAK
+    bound_hbm = issue is None or t_hbm >= issue["issue_floor_us"] / 1e6
+    hbm = {"bound": "hbm", "achieved": round(ro["gbs"], 1), "peak": HBM_PEAK / 1e9, "unit": "GB/s",
+           "frac": round(ro["hbm_frac"], 4), "traffic": measured_traffic(kernel_key, args.N),
+           # old + new state fit the Infinity Cache: the bytes are served from
+           # it, so this is not a fraction of HBM bandwidth actually used
+           "mall_resident": bool(ro["bytes_per_launch"] <= MALL_BYTES)}
+    roofline = {**(hbm if bound_hbm else issue),
+                "kernel": kernel_key,
+                "launch_us": round(ro["launch_us"], 2),
+                "bytes_per_launch": ro["bytes_per_launch"],
+                "issue_roof": issue,
+                "hbm_roof": hbm,
+                "flop_roof": {"bound": "alu", "achieved": round(ro["tflops"], 3), "unit": "TFLOP/s",
+                              "peak": FP64_VALU_PEAK / 1e12, "frac": round(ro["alu_frac"], 4),
+                              "note": "algorithmic flops (fma = 2, a division or square root = 1)"}}
+    if not bound_hbm:
+        roofline["traffic"] = hbm["traffic"]
 
     line = {
         "metric": "cell-DOF updates/s, 1D Euler P=3 (FP64 vs FP32-mixed); batched solves/s",
@@ -512,11 +621,14 @@ def main():
     }
     if rmx is not None:
         rm = roof(rmx, "fp32_mixed")
+        mkey = f"k_half_step<euler,P={args.P},limiter,f32,variant={rmx['launch']['variant']}>"
         line["fp32_mixed"] = {"value": rmx["value"], "unit": "cell-DOF updates/s", "dtype": "f32 bulk + f64 average",
                               "ms_per_step": rmx["wall_s"] * 1e3 / args.steps, "valid": bool(rmx["ok"]),
                               "launch_us": round(rm["launch_us"], 2), "hbm_frac": round(rm["hbm_frac"], 4),
+                              "mall_resident": bool(rm["bytes_per_launch"] <= MALL_BYTES),
                               "gbs": round(rm["gbs"], 1), "tflops": round(rm["tflops"], 3),
-                              "launch": rmx["launch"]}
+                              "issue_roof": issue_roof(mkey, args.N, rm["launch_us"] / 1e6),
+                              "vs_fp64": rmx["vs_fp64"], "launch": rmx["launch"]}
     if rb is not None:
         line["batched"] = rb
     if r2 is not None:

@@ -55,6 +55,8 @@ def _load():
     lib = ctypes.CDLL(_LIB_PATH)
     P = ctypes.POINTER
     dp = P(ctypes.c_double)
+    lib.wcc_oracle_threads.argtypes = []
+    lib.wcc_oracle_threads.restype = ctypes.c_int
     lib.wcc_oracle_ncells.argtypes = [P(_Problem), ctypes.c_int]
     lib.wcc_oracle_ncells.restype = ctypes.c_int64
     lib.wcc_oracle_half_step.argtypes = [P(_Problem), ctypes.c_int, dp, ctypes.c_double, dp, dp]
@@ -98,6 +100,15 @@ class use_library:
         global _lib, _lib2d, _LIB_PATH
         _lib, _lib2d, _LIB_PATH = self._saved
         return False
+
+
+LIB_OMP_PATH = os.path.join(_HERE, "liboracle_omp.so")
+
+
+def threads() -> int:
+    """Threads one half-step of the loaded build uses (1 unless it is the
+    OpenMP build, liboracle_omp.so, selected with use_library)."""
+    return int(_load().wcc_oracle_threads())
 
 
 def _dp(a: np.ndarray):

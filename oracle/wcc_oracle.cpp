@@ -49,6 +49,9 @@
 #include <cstdint>
 #include <cstring>
 #include <vector>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 namespace {
 
@@ -523,7 +526,12 @@ int half_step(const wcc_oracle_problem& pb, int parity, const double* old_dofs, 
   ck_factors(lam, ck);
 
   // Old cells, with one ghost on each side for the non-periodic odd->even step.
+  // (Cells are independent: the optional OpenMP build splits the loops over
+  // threads without changing any operation; the serial build ignores it.)
   std::vector<OldCell<double>> oc((size_t)n_old + 2);
+#ifdef _OPENMP
+#pragma omp parallel for schedule(static)
+#endif
   for (int64_t j = 0; j < n_old; ++j) {
     double q[NCMAX][PMAX + 1];
     load_cell(pb, old_dofs, n_old, j, q);
@@ -546,8 +554,19 @@ int half_step(const wcc_oracle_problem& pb, int parity, const double* old_dofs, 
     }
   }
 
+  // Largest new wave speed, NaN if any speed is NaN: the result does not
+  // depend on the order in which the cells are visited.
   double smax = 0.0;
   int flags = 0;
+#ifdef _OPENMP
+#pragma omp parallel
+#endif
+  {
+  double smax_t = 0.0;
+  int flags_t = 0;
+#ifdef _OPENMP
+#pragma omp for schedule(static)
+#endif
   for (int64_t j = 0; j < n_new; ++j) {
     int64_t jl, jr;  // indices of the parents in the old cell array (no ghost offset)
     if (pb.bc == BC_PERIODIC) {
@@ -558,10 +577,18 @@ int half_step(const wcc_oracle_problem& pb, int parity, const double* old_dofs, 
       else { jl = j - 1; jr = j; }
     }
     double q[NCMAX][PMAX + 1], sp;
-    flags |= new_cell(pb, lam, oc[(size_t)(jl + 1)], oc[(size_t)(jr + 1)], q, sp);
-    if (sp > smax || std::isnan(sp)) smax = std::isnan(smax) ? smax : sp;
+    flags_t |= new_cell(pb, lam, oc[(size_t)(jl + 1)], oc[(size_t)(jr + 1)], q, sp);
+    if (sp > smax_t || std::isnan(sp)) smax_t = std::isnan(smax_t) ? smax_t : sp;
     for (int c = 0; c < nc; ++c)
       for (int k = 0; k <= P; ++k) new_dofs[((int64_t)c * (P + 1) + k) * n_new + j] = q[c][k];
+  }
+#ifdef _OPENMP
+#pragma omp critical
+#endif
+  {
+    flags |= flags_t;
+    if (smax_t > smax || std::isnan(smax_t)) smax = std::isnan(smax) ? smax : smax_t;
+  }
   }
   *smax_out = smax;
   return flags;
@@ -600,6 +627,16 @@ bool valid(const wcc_oracle_problem* pb) {
 }  // namespace
 
 extern "C" {
+
+// Threads a half-step uses: 1 in the serial build, the OpenMP team size in
+// the OpenMP build.
+int wcc_oracle_threads() {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
 
 int64_t wcc_oracle_ncells(const wcc_oracle_problem* pb, int parity) {
   if (!valid(pb)) return -1;

@@ -21,6 +21,7 @@
 
 #include "wcc2d.h"
 #include "wcc2d_internal.hpp"
+#include "wcc_ctrl.hpp"
 
 using wcc::Ctrl;
 using wcc2d::Step2Args;

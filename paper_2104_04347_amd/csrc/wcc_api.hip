@@ -21,6 +21,7 @@
 
 #include "wcc.h"
 #include "wcc_internal.hpp"
+#include "wcc_ctrl.hpp"
 
 using wcc::Ctrl;
 using wcc::StepArgs;

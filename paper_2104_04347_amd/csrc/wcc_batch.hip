@@ -33,6 +33,7 @@
 #include "wcc.h"
 #include "wcc_cell.hpp"
 #include "wcc_internal.hpp"
+#include "wcc_ctrl.hpp"
 #include "wcc_tile.hpp"
 
 namespace wcc {

@@ -95,15 +95,4 @@ hipError_t launch_state_speed(const StepArgs<R>& a, int eq, int P, int blocks, h
 template <class R>
 hipError_t occupancy_half_step(int eq, int P, bool lim, int prefetch, int threads, int* blocks_per_cu);
 
-// Stream-ordered update of Ctrl::t_end and Ctrl::cfl.  The values travel as
-// kernel arguments, so no host buffer has to outlive the call.
-hipError_t launch_set_fields(Ctrl* ctrl, double t_end, double cfl, hipStream_t s);
-
-// Per-degree CFL numbers of the batched form, passed by value.
-struct CflByDegree {
-  double v[5];
-};
-// ctrl[i].cfl = cfl.v[inst[i].P] for the B instances (stream-ordered).
-hipError_t launch_batch_set_cfl(Ctrl* ctrl, const BatchInst* inst, int B, CflByDegree cfl, hipStream_t s);
-
 }  // namespace wcc

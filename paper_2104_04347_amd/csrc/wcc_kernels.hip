@@ -224,29 +224,6 @@ hipError_t occupancy_half_step(int eq, int P, bool lim, int pf, int threads, int
   return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, f, threads, 0);
 }
 
-__global__ void k_set_fields(Ctrl* ctrl, double t_end, double cfl) {
-  if (threadIdx.x == 0) {
-    ctrl->t_end = t_end;
-    ctrl->cfl = cfl;
-  }
-}
-
-hipError_t launch_set_fields(Ctrl* ctrl, double t_end, double cfl, hipStream_t s) {
-  hipLaunchKernelGGL(k_set_fields, dim3(1), dim3(64), 0, s, ctrl, t_end, cfl);
-  return hipGetLastError();
-}
-
-__global__ void k_batch_set_cfl(Ctrl* ctrl, const BatchInst* inst, int B, CflByDegree cfl) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < B) ctrl[i].cfl = cfl.v[inst[i].P];
-}
-
-hipError_t launch_batch_set_cfl(Ctrl* ctrl, const BatchInst* inst, int B, CflByDegree cfl, hipStream_t s) {
-  if (B <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_batch_set_cfl, dim3((B + 255) / 256), dim3(256), 0, s, ctrl, inst, B, cfl);
-  return hipGetLastError();
-}
-
 template hipError_t launch_half_step<double>(const StepArgs<double>&, int, int, bool, int, int, int, hipStream_t);
 template hipError_t launch_half_step<float>(const StepArgs<float>&, int, int, bool, int, int, int, hipStream_t);
 template hipError_t launch_state_speed<double>(const StepArgs<double>&, int, int, int, hipStream_t);

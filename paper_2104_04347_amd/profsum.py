@@ -6,8 +6,18 @@ Measurement tooling; runs on any host, no GPU needed.
       per-kernel dispatch table (calls, total / mean / min / max duration,
       register counts, grid and workgroup sizes) from a --kernel-trace run
 
+  python -m paper_2104_04347_amd.profsum trace DB --last K
+      the same over each kernel's last K dispatches in launch order (the
+      timed half-steps of a run, without its warm-up dispatches)
+
   python -m paper_2104_04347_amd.profsum counters DB
       per-kernel mean / min / max of every counter of a --pmc run
+
+  python -m paper_2104_04347_amd.profsum insts DB --kernel SUBSTR --key NAME --N N
+          [--sources 1d|2d] [--dispatches A:B] [--out profiles/valu_insts.json]
+      mean SQ_INSTS_VALU (64-lane VALU instructions) per dispatch of the
+      kernel whose name contains SUBSTR, from a --pmc run, keyed by NAME and
+      stamped with the kernel sources' hash like the traffic record
 
   python -m paper_2104_04347_amd.profsum traffic FETCH_DB WRITE_DB --kernel SUBSTR
           --key NAME --N N --copy-mib M [--sources 1d|2d] [--dispatches A:B] [--out profiles/traffic.json]
@@ -64,11 +74,18 @@ def kernel_source_hash(sources: str = "1d", read=None) -> str:
     return h.hexdigest()
 
 
-def trace_table(db: str) -> str:
+def trace_table(db: str, last: int = 0) -> str:
     con = sqlite3.connect(db)
-    rows = con.execute("""select name, count(*), sum(duration), avg(duration), min(duration), max(duration),
+    if last > 0:
+        # each kernel's last `last` dispatches (launch order = start time)
+        con.execute(f"""create temp view sel as select * from (select *, row_number() over
+                        (partition by name order by start desc) as rn from kernels) where rn <= {int(last)}""")
+        table = "sel"
+    else:
+        table = "kernels"
+    rows = con.execute(f"""select name, count(*), sum(duration), avg(duration), min(duration), max(duration),
                           max(vgpr_count), max(accum_vgpr_count), max(sgpr_count), max(grid_x), max(workgroup_x)
-                          from kernels group by name order by sum(duration) desc""").fetchall()
+                          from {table} group by name order by sum(duration) desc""").fetchall()
     tot = sum(r[2] for r in rows) or 1
     out = [f"{'kernel':72s} {'calls':>6s} {'total_us':>10s} {'avg_us':>9s} {'min_us':>9s} {'max_us':>9s} "
            f"{'%':>6s} vgpr agpr sgpr grid wg"]
@@ -146,11 +163,48 @@ def traffic(fetch_db: str, write_db: str, match: str, key: str, N: int, copy_mib
     return rec
 
 
+def insts(db: str, match: str, key: str, N: int, out: str | None, sources: str = "1d",
+          select: slice = slice(None)) -> dict:
+    agg = counter_values(db)
+    ks = [k for k in agg if match in k]
+    if len(ks) != 1:
+        raise SystemExit(f"{db}: {len(ks)} kernels match {match!r}: {ks}")
+    vals = (agg[ks[0]].get("SQ_INSTS_VALU") or [])[select]
+    if not vals:
+        raise SystemExit(f"{db}: no SQ_INSTS_VALU values for {ks[0]}")
+    waves = (agg[ks[0]].get("SQ_WAVES") or [])[select]
+    rec = {"kernel_name": ks[0], "source_sha256": kernel_source_hash(sources), "sources": sources, "N": N,
+           "dispatches": len(vals), "sq_insts_valu": statistics.fmean(vals),
+           "sq_insts_valu_min": min(vals), "sq_insts_valu_max": max(vals)}
+    if waves:
+        rec["sq_waves"] = statistics.fmean(waves)
+    if out:
+        try:
+            with open(out) as f:
+                allrec = json.load(f)
+        except (OSError, ValueError):
+            allrec = {}
+        allrec[key] = rec
+        with open(out, "w") as f:
+            json.dump(allrec, f, indent=1, sort_keys=True)
+            f.write("\n")
+    return rec
+
+
 def main(argv=None) -> None:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     sub = ap.add_subparsers(dest="cmd", required=True)
     t = sub.add_parser("trace")
     t.add_argument("db")
+    t.add_argument("--last", type=int, default=0, help="only each kernel's last K dispatches")
+    i = sub.add_parser("insts")
+    i.add_argument("db")
+    i.add_argument("--kernel", required=True)
+    i.add_argument("--key", required=True)
+    i.add_argument("--N", type=int, required=True)
+    i.add_argument("--sources", choices=("1d", "2d"), default="1d")
+    i.add_argument("--dispatches", default=":")
+    i.add_argument("--out")
     c = sub.add_parser("counters")
     c.add_argument("db")
     r = sub.add_parser("traffic")
@@ -166,9 +220,13 @@ def main(argv=None) -> None:
     r.add_argument("--out")
     a = ap.parse_args(argv)
     if a.cmd == "trace":
-        print(trace_table(a.db))
+        print(trace_table(a.db, a.last))
     elif a.cmd == "counters":
         print(counters_table(a.db))
+    elif a.cmd == "insts":
+        lo, hi = (int(v) if v else None for v in a.dispatches.split(":"))
+        json.dump(insts(a.db, a.kernel, a.key, a.N, a.out, a.sources, slice(lo, hi)), sys.stdout, indent=1)
+        print()
     else:
         lo, hi = (int(v) if v else None for v in a.dispatches.split(":"))
         json.dump(traffic(a.fetch_db, a.write_db, a.kernel, a.key, a.N, a.copy_mib, a.out, a.sources, slice(lo, hi)),

@@ -95,6 +95,7 @@ def test_large_mixed_within_tolerance(large_case, variant):
     for c in range(3):
         S = np.abs(ref.q[c, 0]).max()
         err = np.abs(q[c, 0] - ref.q[c, 0])
+        print(f"large mixed v{variant} c={c}: Linf/S {err.max() / S:.3e} L1/S {err.mean() / S:.3e}", flush=True)
         assert err.mean() <= 4 * np.sqrt(n) * U32 * S, (c, err.mean() / S)
         assert err.max() <= 1e-2 * S, (c, err.max() / S)
     # the totals are sequential binary64 sums over N cells: each evaluation

@@ -81,12 +81,40 @@ def test_traffic_scaling_and_dispatch_selection(tmp_path, monkeypatch):
 
 
 def test_committed_records_match_the_sources():
-    """The committed counter record belongs to the kernels as they are."""
+    """The committed counter records belong to the kernels as they are."""
     rec = json.load(open(os.path.join(bench.ROOT, "profiles", "traffic.json")))
     assert rec, "no records"
     for key, e in rec.items():
         assert e["source_sha256"] == profsum.kernel_source_hash(e.get("sources", "1d")), key
         assert bench.measured_traffic(key, e["N"], e.get("sources", "1d")) > 0
+    path = os.path.join(bench.ROOT, "profiles", "valu_insts.json")
+    if os.path.exists(path):
+        for key, e in json.load(open(path)).items():
+            assert e["source_sha256"] == profsum.kernel_source_hash(e.get("sources", "1d")), key
+            assert bench.valu_insts(key, e["N"], e.get("sources", "1d")) > 0
+
+
+def test_valu_instruction_record_and_issue_roof(tmp_path, monkeypatch):
+    """SQ_INSTS_VALU per dispatch -> record -> issue roof: instructions at one
+    per 4 cycles on 1024 SIMDs at 2.4 GHz, against the launch time."""
+    k = "void wcc::k_half_step<2, 3, true, double, 0>(args)"
+    rows = [(i, k, "SQ_INSTS_VALU", 1.0e6 + (i % 2) * 2.0) for i in range(6)]
+    rows += [(i, k, "SQ_WAVES", 3072.0) for i in range(6)]
+    _fake_db(tmp_path / "i.db", rows)
+    out = tmp_path / "valu_insts.json"
+    rec = profsum.insts(str(tmp_path / "i.db"), "k_half_step<2, 3, true, double, 0>", "key1", 128, str(out))
+    assert rec["sq_insts_valu"] == 1.0e6 + 1.0 and rec["sq_waves"] == 3072.0 and rec["dispatches"] == 6
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    (tmp_path / "profiles").mkdir()
+    (tmp_path / "profiles" / "valu_insts.json").write_text(out.read_text())
+    assert bench.valu_insts("key1", 128) == rec["sq_insts_valu"]
+    assert bench.valu_insts("key1", 129) is None
+    launch_s = 10e-6
+    r = bench.issue_roof("key1", 128, launch_s)
+    floor = rec["sq_insts_valu"] * 4 / (1024 * 2.4e9)
+    assert abs(r["frac"] - round(floor / launch_s, 4)) < 1e-12
+    assert abs(r["issue_floor_us"] - round(floor * 1e6, 2)) < 1e-12
+    assert bench.issue_roof("key1", 129, launch_s) is None
 
 
 def test_autotune_keys():
