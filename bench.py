@@ -123,11 +123,21 @@ def launch_shape_single(args, s, q0, cfl=None, **tune_kw) -> dict:
         return {**s.get_launch(), "source": "library default"}
     if args.tune == "auto" and autotune.apply_single(s):
         c = autotune.cached_single(s)
-        return {"threads": c["threads"], "blocks": c["blocks"], "variant": c.get("variant", 0),
+        v = c.get("variant", 0)
+        return {"threads": c["threads"], "blocks": c["blocks"], "variant": v, "tile": autotune.TILE_SHAPE[v],
                 "source": "autotune cache"}
     best = autotune.tune_single(s, q0, args.cfl if cfl is None else cfl, **tune_kw)
-    return {"threads": best["threads"], "blocks": best["blocks"], "variant": best["variant"], "source": "autotuned",
+    return {"threads": best["threads"], "blocks": best["blocks"], "variant": best["variant"], "tile": best["tile"],
+            "source": "autotuned",
             "best_us_per_variant": {str(v): round(ms * 1e3, 2) for v, ms in best["per_variant_ms"].items()}}
+
+
+def kernel_record(precision: str, P: int, variant: int):
+    """Key and source set of the counter records of the 1D Euler kernel."""
+    bulk = "f64" if precision == "fp64" else "f32"
+    if variant == 4:
+        return f"k_half_step_wide<euler,P={P},limiter,{bulk}>", "1d_wide"
+    return f"k_half_step<euler,P={P},limiter,{bulk},variant={variant}>", "1d"
 
 
 def time_single(args, precision: str, q0, keep_state: bool = False):
@@ -574,16 +584,16 @@ def main():
                     tflops=flops / 1e12, alu_frac=flops / peak_alu, alu_peak=peak_alu)
 
     ro = roof(r64, "fp64")
-    # the counter records are per kernel variant (prefetch / staged stores)
-    kernel_key = f"k_half_step<euler,P={args.P},limiter,f64,variant={r64['launch']['variant']}>"
+    # the counter records are per kernel variant (prefetch / staged stores / tile shape)
+    kernel_key, ksrc = kernel_record("fp64", args.P, r64["launch"]["variant"])
     launch_s = ro["launch_us"] / 1e6
-    issue = issue_roof(kernel_key, args.N, launch_s)
+    issue = issue_roof(kernel_key, args.N, launch_s, ksrc)
     # the binding roof is the one with the longer floor: algorithmic bytes at
     # the HBM peak, or the measured VALU instructions at the issue peak
     t_hbm = ro["bytes_per_launch"] / HBM_PEAK
     bound_hbm = issue is None or t_hbm >= issue["issue_floor_us"] / 1e6
     hbm = {"bound": "hbm", "achieved": round(ro["gbs"], 1), "peak": HBM_PEAK / 1e9, "unit": "GB/s",
-           "frac": round(ro["hbm_frac"], 4), "traffic": measured_traffic(kernel_key, args.N),
+           "frac": round(ro["hbm_frac"], 4), "traffic": measured_traffic(kernel_key, args.N, ksrc),
            # old + new state fit the Infinity Cache: the bytes are served from
            # it, so this is not a fraction of HBM bandwidth actually used
            "mall_resident": bool(ro["bytes_per_launch"] <= MALL_BYTES)}
@@ -621,13 +631,13 @@ def main():
     }
     if rmx is not None:
         rm = roof(rmx, "fp32_mixed")
-        mkey = f"k_half_step<euler,P={args.P},limiter,f32,variant={rmx['launch']['variant']}>"
+        mkey, msrc = kernel_record("fp32_mixed", args.P, rmx["launch"]["variant"])
         line["fp32_mixed"] = {"value": rmx["value"], "unit": "cell-DOF updates/s", "dtype": "f32 bulk + f64 average",
                               "ms_per_step": rmx["wall_s"] * 1e3 / args.steps, "valid": bool(rmx["ok"]),
                               "launch_us": round(rm["launch_us"], 2), "hbm_frac": round(rm["hbm_frac"], 4),
                               "mall_resident": bool(rm["bytes_per_launch"] <= MALL_BYTES),
                               "gbs": round(rm["gbs"], 1), "tflops": round(rm["tflops"], 3),
-                              "issue_roof": issue_roof(mkey, args.N, rm["launch_us"] / 1e6),
+                              "issue_roof": issue_roof(mkey, args.N, rm["launch_us"] / 1e6, msrc),
                               "vs_fp64": rmx["vs_fp64"], "launch": rmx["launch"]}
     if rb is not None:
         line["batched"] = rb

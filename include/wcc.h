@@ -184,14 +184,16 @@ int wcc_totals(wcc_ctx* ctx, double* per_component);
 /* Launch shape of the half-step kernel (not a paper quantity: the work
  * decomposition only; results do not depend on it): threads per block (64,
  * 128, 192 or 256; 0 = 256), blocks (0 = enough to fill the device at the
- * kernel's occupancy) and kernel variant, a sum of bits: 1 = load the next
- * tile's inputs while computing the current one; 2 = store the new cells in
- * whole 64-cell groups staged through LDS instead of one 63-cell tile per
- * wave (pays when the state does not fit the caches); 0 is neither; -1 keeps
- * the current variant.  At creation the variant is 3 when the two state
- * buffers exceed 512 MiB, else 1.  Used by the autotuner.  Errors:
- * WCC_EINVAL (variant outside -1..3, threads not 64..256 in steps of 64,
- * negative blocks). */
+ * kernel's occupancy) and kernel variant.  Variants 0..3 use wave tiles of
+ * 64 old cells (one per lane, 63 new cells) and are a sum of bits: 1 = load
+ * the next tile's inputs while computing the current one; 2 = store the new
+ * cells in whole 64-cell groups staged through LDS instead of one 63-cell
+ * tile per wave (pays when the state does not fit the caches).  Variant 4
+ * is the second tile shape: wave tiles of 128 old cells, two per lane (127
+ * new cells), direct stores.  -1 keeps the current variant.  At creation the
+ * variant is 3 when the two state buffers exceed 512 MiB, else 1.  Used by
+ * the autotuner.  Errors: WCC_EINVAL (variant outside -1..4, threads not
+ * 64..256 in steps of 64, negative blocks). */
 int wcc_set_launch(wcc_ctx* ctx, int threads_per_block, int blocks, int variant);
 
 /* The current launch shape: threads per block, blocks (0 = device-filling

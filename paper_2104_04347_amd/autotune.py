@@ -59,8 +59,13 @@ def key_single(equation: str, P: int, N: int, precision: str, limiter: bool) -> 
     return f"single/{equation}/P{P}/{precision}/{'lim' if limiter else 'nolim'}/N2^{int(np.log2(max(N, 2)))}"
 
 
+# wave-tile shape of each single-instance launch variant: old cells per tile
+# and per lane (variants 0-3 differ in prefetch and staged stores only)
+TILE_SHAPE = {0: "64x1", 1: "64x1", 2: "64x1", 3: "64x1", 4: "128x2"}
+
+
 def tune_single(solver: "binding.Solver", q0: np.ndarray, cfl: float, steps: int = 480,
-                threads=(128, 256), block_factors=(0, 2, 3, 4, 5, 6, 8), variants=(0, 1, 2, 3),
+                threads=(128, 256), block_factors=(0, 2, 3, 4, 5, 6, 8), variants=(0, 1, 2, 3, 4),
                 verbose: bool = False) -> dict:
     """Time the candidate shapes on `solver` (state q0, CFL cfl); keep the best.
     Blocks per launch = block factor x compute units; factor 0 = the
@@ -94,10 +99,12 @@ def tune_single(solver: "binding.Solver", q0: np.ndarray, cfl: float, steps: int
         best = {**default, "ms_per_step": default_ms}
     best["default_ms_per_step"] = default_ms
     best["per_variant_ms"] = {v: min(r["ms_per_step"] for r in results if r["variant"] == v) for v in variants}
+    best["tile"] = TILE_SHAPE[best["variant"]]
     best["tried"] = results
     c = _load_cache()
     c[key_single(solver.equation, solver.P, solver.N, binding.PRECISIONS_NAME[solver.params.precision],
-                 bool(solver.params.limiter))] = {k: best[k] for k in ("variant", "threads", "blocks", "ms_per_step")}
+                 bool(solver.params.limiter))] = {k: best[k] for k in ("variant", "tile", "threads", "blocks",
+                                                                      "ms_per_step")}
     _save_cache(c)
     solver.set_launch(best["threads"], best["blocks"], best["variant"])
     return best

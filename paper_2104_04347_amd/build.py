@@ -19,7 +19,7 @@ OUT_DIR = os.path.join(HERE, "_lib")
 LIB = os.path.join(OUT_DIR, "libwcc.so")
 ROOT = os.path.dirname(HERE)
 
-SOURCES = ["wcc_kernels.hip", "wcc_ctrl.hip", "wcc_batch.hip", "wcc_api.hip", "wcc2d_kernels.hip", "wcc2d_api.hip"]
+SOURCES = ["wcc_kernels.hip", "wcc_kernels_wide.hip", "wcc_ctrl.hip", "wcc_batch.hip", "wcc_api.hip", "wcc2d_kernels.hip", "wcc2d_api.hip"]
 ARCH = "gfx950"
 
 HIPFLAGS = [

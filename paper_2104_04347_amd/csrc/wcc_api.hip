@@ -16,12 +16,14 @@
 #include <cstdio>
 #include <cstring>
 #include <limits>
+#include <map>
 #include <string>
 #include <vector>
 
 #include "wcc.h"
 #include "wcc_internal.hpp"
 #include "wcc_ctrl.hpp"
+#include "wcc_wide.hpp"
 
 using wcc::Ctrl;
 using wcc::StepArgs;
@@ -29,6 +31,7 @@ using wcc::StepArgs;
 namespace {
 
 constexpr int kChunk = 48;  // half-steps per captured graph (multiple of 6)
+constexpr int kWideVariant = 4;  // launch variant: 128-cell wave tiles, two old cells per lane
 
 inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
@@ -61,7 +64,9 @@ struct wcc_ctx {
   int prefetch = 1;          // kernel variant bits: 1 = prefetch the next tile's inputs, 2 = aligned stores
   int cu = 0;
   hipStream_t capture = nullptr;
-  hipGraphExec_t graphs[6] = {};
+  // captured runs of `len` half-steps from (slot, parity), key (len*3 + slot)*2 + parity:
+  // full chunks (len = kChunk) and the remainders of runs (len < kChunk)
+  std::map<int, hipGraphExec_t> graphs;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   double last_run_ms = 0.0;
   std::string err;
@@ -106,13 +111,24 @@ wcc::Phys<R> phys_of(const wcc_ctx* c) {
   return ph;
 }
 
+// Device addresses a half-step works on: the time-control block, the
+// partial wave-speed maxima and the two state buffers.
+struct Lay {
+  Ctrl* ctrl;
+  unsigned long long* parts;
+  double* p[2];
+  void* d[2];
+};
+
+Lay bound_lay(const wcc_ctx* c) { return Lay{c->ctrl, c->parts, {c->p[0], c->p[1]}, {c->d[0], c->d[1]}}; }
+
 template <class R>
-StepArgs<R> args_for(const wcc_ctx* c, int parity, int slot, double dt_fixed) {
+StepArgs<R> args_at(const wcc_ctx* c, const Lay& L, int parity, int slot, double dt_fixed) {
   StepArgs<R> a{};
-  a.p_old = c->p[parity];
-  a.d_old = static_cast<const R*>(c->d[parity]);
-  a.p_new = c->p[1 - parity];
-  a.d_new = static_cast<R*>(c->d[1 - parity]);
+  a.p_old = L.p[parity];
+  a.d_old = static_cast<const R*>(L.d[parity]);
+  a.p_new = L.p[1 - parity];
+  a.d_new = static_cast<R*>(L.d[1 - parity]);
   a.ld = c->ld;
   a.n_old = ncells_of(c, parity);
   a.n_new = ncells_of(c, 1 - parity);
@@ -122,55 +138,84 @@ StepArgs<R> args_for(const wcc_ctx* c, int parity, int slot, double dt_fixed) {
   a.dx = dx_of(c);
   a.dt_fixed = dt_fixed;
   a.ph = phys_of<R>(c);
-  a.ctrl = c->ctrl;
-  a.parts = c->parts;
+  a.ctrl = L.ctrl;
+  a.parts = L.parts;
   a.slot = slot;
   return a;
 }
 
+template <class R>
+StepArgs<R> args_for(const wcc_ctx* c, int parity, int slot, double dt_fixed) {
+  return args_at<R>(c, bound_lay(c), parity, slot, dt_fixed);
+}
+
 int blocks_for(wcc_ctx* c) {
   if (c->blocks > 0) return c->blocks;
-  const int64_t tiles = (std::max(ncells_of(c, 0), ncells_of(c, 1)) + 62) / 63;
+  const bool wide = c->prefetch == kWideVariant;
+  const int64_t span = wide ? 127 : 63;   // new cells per wave tile
+  const int64_t tiles = (std::max(ncells_of(c, 0), ncells_of(c, 1)) + span - 1) / span;
   const int waves = c->threads / 64;
   int per_cu = 0;
-  hipError_t e = c->prm.precision == WCC_FP64
-                     ? wcc::occupancy_half_step<double>(c->eq, c->P, c->prm.limiter != 0, c->prefetch, c->threads,
-                                                        &per_cu)
-                     : wcc::occupancy_half_step<float>(c->eq, c->P, c->prm.limiter != 0, c->prefetch, c->threads,
-                                                       &per_cu);
+  const bool lim = c->prm.limiter != 0;
+  hipError_t e;
+  if (wide)
+    e = c->prm.precision == WCC_FP64 ? wcc::occupancy_half_step_wide<double>(c->eq, c->P, lim, c->threads, &per_cu)
+                                     : wcc::occupancy_half_step_wide<float>(c->eq, c->P, lim, c->threads, &per_cu);
+  else
+    e = c->prm.precision == WCC_FP64
+            ? wcc::occupancy_half_step<double>(c->eq, c->P, lim, c->prefetch, c->threads, &per_cu)
+            : wcc::occupancy_half_step<float>(c->eq, c->P, lim, c->prefetch, c->threads, &per_cu);
   if (e != hipSuccess || per_cu < 1) per_cu = 1;
   int64_t full = (int64_t)per_cu * c->cu;
   int64_t need = (tiles + waves - 1) / waves;
   return (int)std::max<int64_t>(1, std::min(full, need));
 }
 
-// Enqueue one half-step kernel: launch number `launched` -> slot and buffers.
-int enqueue_step(wcc_ctx* c, int parity, int slot, double dt_fixed, hipStream_t s) {
+// Enqueue one half-step kernel on the buffers of L: launch number `launched`
+// -> slot and buffers.
+int enqueue_step_at(wcc_ctx* c, const Lay& L, int parity, int slot, double dt_fixed, hipStream_t s) {
   const int blocks = blocks_for(c);
   hipError_t e;
-  if (c->prm.precision == WCC_FP64)
-    e = wcc::launch_half_step<double>(args_for<double>(c, parity, slot, dt_fixed), c->eq, c->P, c->prm.limiter != 0,
-                                      c->prefetch, blocks, c->threads, s);
+  if (c->prefetch == kWideVariant) {
+    if (c->prm.precision == WCC_FP64)
+      e = wcc::launch_half_step_wide<double>(args_at<double>(c, L, parity, slot, dt_fixed), c->eq, c->P,
+                                             c->prm.limiter != 0, blocks, c->threads, s);
+    else
+      e = wcc::launch_half_step_wide<float>(args_at<float>(c, L, parity, slot, dt_fixed), c->eq, c->P,
+                                            c->prm.limiter != 0, blocks, c->threads, s);
+  } else if (c->prm.precision == WCC_FP64)
+    e = wcc::launch_half_step<double>(args_at<double>(c, L, parity, slot, dt_fixed), c->eq, c->P,
+                                      c->prm.limiter != 0, c->prefetch, blocks, c->threads, s);
   else
-    e = wcc::launch_half_step<float>(args_for<float>(c, parity, slot, dt_fixed), c->eq, c->P, c->prm.limiter != 0,
-                                     c->prefetch, blocks, c->threads, s);
+    e = wcc::launch_half_step<float>(args_at<float>(c, L, parity, slot, dt_fixed), c->eq, c->P,
+                                     c->prm.limiter != 0, c->prefetch, blocks, c->threads, s);
   if (e != hipSuccess) return fail(c, WCC_EDEVICE, "half-step launch: %s", hipGetErrorString(e));
   return WCC_OK;
 }
 
+int enqueue_step(wcc_ctx* c, int parity, int slot, double dt_fixed, hipStream_t s) {
+  return enqueue_step_at(c, bound_lay(c), parity, slot, dt_fixed, s);
+}
+
 int current_parity(const wcc_ctx* c) { return (int)((c->parity_w + c->steps) & 1); }
 
-// Graph of kChunk consecutive half-steps starting at (slot0, parity0).
-int chunk_graph(wcc_ctx* c, int slot0, int parity0, hipGraphExec_t* out) {
-  const int key = slot0 * 2 + parity0;
-  if (c->graphs[key]) {
-    *out = c->graphs[key];
+void drop_graphs(wcc_ctx* c) {
+  for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
+  c->graphs.clear();
+}
+
+// Graph of `len` (1..kChunk) consecutive half-steps starting at (slot0, parity0).
+int chunk_graph(wcc_ctx* c, int slot0, int parity0, hipGraphExec_t* out, int len = kChunk) {
+  const int key = (len * 3 + slot0) * 2 + parity0;
+  auto it = c->graphs.find(key);
+  if (it != c->graphs.end()) {
+    *out = it->second;
     return WCC_OK;
   }
   if (!c->capture) HIPCHK(c, hipStreamCreateWithFlags(&c->capture, hipStreamNonBlocking));
   HIPCHK(c, hipStreamBeginCapture(c->capture, hipStreamCaptureModeThreadLocal));
   int rc = WCC_OK;
-  for (int i = 0; i < kChunk && rc == WCC_OK; ++i)
+  for (int i = 0; i < len && rc == WCC_OK; ++i)
     rc = enqueue_step(c, (parity0 + i) & 1, (slot0 + i) % 3, 0.0, c->capture);
   hipGraph_t g = nullptr;
   hipError_t e = hipStreamEndCapture(c->capture, &g);
@@ -281,8 +326,7 @@ int wcc_bind(wcc_ctx* c, void* dev_ptr, size_t bytes, void* hip_stream) {
   size_t need = 0;
   wcc_workspace_bytes(c, &need);
   if (bytes < need) return fail(c, WCC_ESIZE, "workspace of %zu bytes, need %zu", bytes, need);
-  for (auto& g : c->graphs)
-    if (g) { (void)hipGraphExecDestroy(g); g = nullptr; }
+  drop_graphs(c);
   c->ws = static_cast<char*>(dev_ptr);
   c->ws_bytes = bytes;
   c->stream = static_cast<hipStream_t>(hip_stream);
@@ -393,14 +437,22 @@ int wcc_step(wcc_ctx* c, double cfl, double dt_fixed) {
 }
 
 static int run_chunks(wcc_ctx* c, int64_t n, bool timed) {
-  // Build every chunk graph a run can start on before the first one is
-  // needed, so that no capture or instantiation falls between the events.
+  // Build every chunk graph a run can start on, and the graph of its
+  // remainder, before the first one is needed, so that no capture or
+  // instantiation falls between the events.
   if (n >= kChunk) {
     for (int key = 0; key < 6; ++key) {
       hipGraphExec_t g;
       const int rc = chunk_graph(c, key / 2, key % 2, &g);
       if (rc) return rc;
     }
+  }
+  const int rem = (int)(n % kChunk);
+  if (rem > 0) {
+    const int64_t at = c->launched + (n - rem);
+    hipGraphExec_t g;
+    const int rc = chunk_graph(c, (int)(at % 3), (int)((c->parity_w + c->steps + (n - rem)) & 1), &g, rem);
+    if (rc) return rc;
   }
   if (timed) {
     if (!c->ev0) HIPCHK(c, hipEventCreate(&c->ev0));
@@ -419,11 +471,13 @@ static int run_chunks(wcc_ctx* c, int64_t n, bool timed) {
       c->steps += kChunk;
       left -= kChunk;
     } else {
-      int rc = enqueue_step(c, par, slot, 0.0, c->stream);
+      hipGraphExec_t g;
+      int rc = chunk_graph(c, slot, par, &g, (int)left);
       if (rc) return rc;
-      c->launched += 1;
-      c->steps += 1;
-      left -= 1;
+      HIPCHK(c, hipGraphLaunch(g, c->stream));
+      c->launched += left;
+      c->steps += left;
+      left = 0;
     }
   }
   if (timed) HIPCHK(c, hipEventRecord(c->ev1, c->stream));
@@ -578,15 +632,14 @@ int wcc_get_launch(const wcc_ctx* c, int* threads_per_block, int* blocks, int* v
 
 int wcc_set_launch(wcc_ctx* c, int threads_per_block, int blocks, int variant) {
   if (!c) return WCC_EINVAL;
-  if (variant < -1 || variant > 3) return fail(c, WCC_EINVAL, "variant must be -1 (keep) or 0..3");
+  if (variant < -1 || variant > kWideVariant) return fail(c, WCC_EINVAL, "variant must be -1 (keep) or 0..4");
   if (variant >= 0) c->prefetch = variant;
   if (threads_per_block != 0 && (threads_per_block % 64 != 0 || threads_per_block < 64 || threads_per_block > 256))
     return fail(c, WCC_EINVAL, "threads per block must be 64, 128, 192 or 256");
   if (blocks < 0) return fail(c, WCC_EINVAL, "negative block count");
   c->threads = threads_per_block ? threads_per_block : 256;
   c->blocks = blocks;
-  for (auto& g : c->graphs)
-    if (g) { (void)hipGraphExecDestroy(g); g = nullptr; }
+  drop_graphs(c);
   return WCC_OK;
 }
 
@@ -606,8 +659,7 @@ const char* wcc_last_error(const wcc_ctx* c) { return c ? c->err.c_str() : "null
 
 void wcc_destroy(wcc_ctx* c) {
   if (!c) return;
-  for (auto& g : c->graphs)
-    if (g) (void)hipGraphExecDestroy(g);
+  drop_graphs(c);
   if (c->capture) (void)hipStreamDestroy(c->capture);
   if (c->ev0) (void)hipEventDestroy(c->ev0);
   if (c->ev1) (void)hipEventDestroy(c->ev1);

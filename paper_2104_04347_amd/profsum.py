@@ -26,7 +26,8 @@ Measurement tooling; runs on any host, no GPU needed.
       scaled by what the same counter reads for the runtime's device-to-device
       copy of M MiB profiled in the same run (the largest copy dispatch).  The
       record is keyed by NAME and stamped with the SHA-256 of the kernel
-      sources' code (the 1D or the 2D half-step's, comments removed), so that
+      sources' code (the 1D, the 1D two-cells-per-lane or the 2D half-step's,
+      comments removed: --sources 1d | 1d_wide | 2d), so that
       a later kernel change invalidates it.
 """
 from __future__ import annotations
@@ -49,6 +50,9 @@ COPY_KERNEL = "__amd_rocclr_copyBuffer"
 # those of the 2D half-step kernels
 KERNEL_SOURCES = ("wcc_cell.hpp", "wcc_internal.hpp", "wcc_kernels.hip", "wcc_tile.hpp")
 KERNEL_SOURCES_2D = ("wcc2d_cell.hpp", "wcc2d_internal.hpp", "wcc2d_kernels.hip", "wcc_internal.hpp", "wcc_tile.hpp")
+# the 1D kernel with two old cells per lane (launch variant 4)
+KERNEL_SOURCES_WIDE = ("wcc_cell.hpp", "wcc_internal.hpp", "wcc_kernels_wide.hip", "wcc_tile.hpp", "wcc_wide.hpp")
+SOURCE_SETS = {"1d": KERNEL_SOURCES, "2d": KERNEL_SOURCES_2D, "1d_wide": KERNEL_SOURCES_WIDE}
 
 
 def code_only(text: str) -> str:
@@ -69,7 +73,7 @@ def kernel_source_hash(sources: str = "1d", read=None) -> str:
             with open(os.path.join(CSRC, name)) as f:
                 return f.read()
     h = hashlib.sha256()
-    for name in (KERNEL_SOURCES if sources == "1d" else KERNEL_SOURCES_2D):
+    for name in SOURCE_SETS[sources]:
         h.update(name.encode() + b"\0" + code_only(read(name)).encode())
     return h.hexdigest()
 
@@ -202,7 +206,7 @@ def main(argv=None) -> None:
     i.add_argument("--kernel", required=True)
     i.add_argument("--key", required=True)
     i.add_argument("--N", type=int, required=True)
-    i.add_argument("--sources", choices=("1d", "2d"), default="1d")
+    i.add_argument("--sources", choices=tuple(SOURCE_SETS), default="1d")
     i.add_argument("--dispatches", default=":")
     i.add_argument("--out")
     c = sub.add_parser("counters")
@@ -214,7 +218,7 @@ def main(argv=None) -> None:
     r.add_argument("--key", required=True)
     r.add_argument("--N", type=int, required=True)
     r.add_argument("--copy-mib", type=int, required=True)
-    r.add_argument("--sources", choices=("1d", "2d"), default="1d")
+    r.add_argument("--sources", choices=tuple(SOURCE_SETS), default="1d")
     r.add_argument("--dispatches", default=":",
                    help="A:B, the kernel's dispatches A to B-1 in launch order (a kernel run by several legs)")
     r.add_argument("--out")

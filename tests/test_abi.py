@@ -79,7 +79,7 @@ def test_workspace_size_and_state_errors_without_gpu():
     assert lib.wcc_create(2, 4, 1 << 24, 0, ctypes.byref(p), ctypes.byref(big)) == 0
     assert lib.wcc_get_launch(big, ctypes.byref(t), ctypes.byref(b), ctypes.byref(v)) == 0 and v.value == 3
     lib.wcc_destroy(big)
-    assert lib.wcc_set_launch(h, 128, 0, 4) == binding.WCC_EINVAL
+    assert lib.wcc_set_launch(h, 128, 0, 5) == binding.WCC_EINVAL
     assert lib.wcc_set_launch(h, 128, 0, -2) == binding.WCC_EINVAL
     lib.wcc_destroy(h)
     pm = binding.make_params(precision="fp32_mixed")

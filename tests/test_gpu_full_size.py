@@ -83,9 +83,10 @@ def test_large_fp64_bitwise(large_case, variant):
 @pytest.mark.parametrize("variant", [0, 3])
 def test_large_mixed_within_tolerance(large_case, variant):
     """Two half-steps in FP32-mixed against the FP64 oracle: point-value L1
-    within 4 sqrt(n) u32 S, Linf within 1e-2 S (the weights switch at
-    slightly different places in binary32 at the jumps), conserved totals
-    within the round-off of their own binary64 evaluation."""
+    within 4 sqrt(n) u32 S, Linf within n C u32 S with C = 128 (the bound on
+    binary32 roundings along the longest dependent chain to a new DOF, as in
+    test_gpu_parity.MIXED_LINF_C), conserved totals within the round-off of
+    their own binary64 evaluation."""
     q0, ref = large_case
     q, info, tot0, tot = _large_gpu(q0, "fp32_mixed", variant)
     print(f"large mixed variant {variant}", flush=True)
@@ -97,7 +98,7 @@ def test_large_mixed_within_tolerance(large_case, variant):
         err = np.abs(q[c, 0] - ref.q[c, 0])
         print(f"large mixed v{variant} c={c}: Linf/S {err.max() / S:.3e} L1/S {err.mean() / S:.3e}", flush=True)
         assert err.mean() <= 4 * np.sqrt(n) * U32 * S, (c, err.mean() / S)
-        assert err.max() <= 1e-2 * S, (c, err.max() / S)
+        assert err.max() <= n * 128 * U32 * S, (c, err.max() / S)
     # the totals are sequential binary64 sums over N cells: each evaluation
     # carries round-off of about sqrt(N) u64 sum|u| (random-walk estimate, a
     # factor 4 above it allowed); binary32 averages would drift by ~1e-8

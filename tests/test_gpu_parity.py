@@ -206,15 +206,8 @@ def test_c3_euler_full_size(P, shape):
 @pytest.mark.parametrize("variant", [0, 1, 2, 3])
 def test_c3_mixed_full_size_vs_oracle(P, variant):
     """FP32-mixed at the benchmark size against the FP64 oracle after n = 6
-    half-steps, in each kernel variant.  Tolerances from the arithmetic:
-    every half-step perturbs a new DOF by at most C u32 S, with S the field's
-    scale and C = 64 a bound on the binary32 roundings along the longest
-    dependent chain to a new DOF (Taylor products and the series quotient of
-    the expansion, the limiter's indicator, ratio, square and normalisation);
-    perturbations pass through the scheme without growth (stable step, the
-    limiter a convex combination), so they add up to at most n C u32 S
-    (Linf); away from the jumps the rounding errors are independent, so the
-    mean stays within 4 sqrt(n) u32 S."""
+    half-steps, in each kernel variant, with the tolerances of MIXED_LINF_C
+    (Linf within n C u32 S) and the mean within 4 sqrt(n) u32 S."""
     n, N = 6, 1 << 20
     q0, ref = _c3_reference(P, n)
     q, info, taken = gpu_run("euler", P, N, "transmissive", q0, limiter=True, steps=n, cfl=0.25,
@@ -225,7 +218,7 @@ def test_c3_mixed_full_size_vs_oracle(P, variant):
         S = np.abs(ref.q[c, 0]).max()
         err = np.abs(q[c, 0] - ref.q[c, 0])
         print(f"C3 mixed P={P} v{variant} c={c}: Linf/S {err.max() / S:.3e} L1/S {err.mean() / S:.3e}", flush=True)
-        assert err.max() <= n * 64 * U32 * S, (c, err.max() / S)
+        assert err.max() <= n * MIXED_LINF_C * U32 * S, (c, err.max() / S)
         assert err.mean() <= 4 * np.sqrt(n) * U32 * S, (c, err.mean() / S)
 
 
@@ -263,6 +256,20 @@ def test_determinism_repeat():
 
 
 U32 = 2.0 ** -24   # binary32 unit round-off
+# Linf tolerance of the FP32-mixed mode against the FP64 oracle, from the
+# arithmetic: one half-step perturbs a new DOF by at most C u32 S (S the
+# field's scale), C bounding the binary32 roundings along the longest
+# dependent chain from the stored DOFs to a new DOF -- for Euler at P = 3
+# about 60 in the expansion (Taylor products and the series quotient, four
+# time levels) and about 50 in the characteristic limiter (projection,
+# indicator, sigma and tau, ratio, square, normalisation, back-projection):
+# C = 128.  The perturbations pass through the scheme without growth (a
+# stable step; the limited polynomial is a convex combination of candidates
+# with weights of bounded sensitivity), so after n half-steps they add up to
+# at most n C u32 S.  Where the rounding errors are independent (everywhere
+# but at the few cells of a jump) the mean error grows like their random
+# walk: within 4 sqrt(n) u32 S.
+MIXED_LINF_C = 128
 
 
 @pytest.mark.parametrize("P", [1, 2, 3, 4])
@@ -293,10 +300,9 @@ def test_mixed_precision_smooth(P):
 
 @pytest.mark.parametrize("P", [2, 3])
 def test_mixed_precision_riemann(P):
-    """FP32-mixed on a seeded Riemann problem (limiter active at the waves):
-    L1 of the density within 1e-5 of the density scale against the FP64
-    oracle after 300 half-steps, Linf within 1e-2 (the limiter weights switch
-    at slightly different places in binary32 at the discontinuities)."""
+    """FP32-mixed on a seeded Riemann problem (limiter active at the waves)
+    against the FP64 oracle after n = 300 half-steps: density Linf within
+    n C u32 S and mean within 4 sqrt(n) u32 S (MIXED_LINF_C)."""
     N = 4000
     q0, _ = inputs.euler_riemann(0, P, N)
     q, info, taken = gpu_run("euler", P, N, "transmissive", q0, limiter=True, steps=300, cfl=0.25,
@@ -305,7 +311,9 @@ def test_mixed_precision_riemann(P):
     scale = np.abs(ref.q[0, 0]).max()
     err = np.abs(q[0, 0] - ref.q[0, 0])
     print(f"Riemann mixed P={P}: Linf/S {err.max() / scale:.3e} L1/S {err.mean() / scale:.3e}", flush=True)
-    assert err.mean() <= 1e-5 * scale and err.max() <= 1e-2 * scale, (err.mean(), err.max())
+    n = 300
+    assert err.mean() <= 4 * np.sqrt(n) * U32 * scale, err.mean() / scale
+    assert err.max() <= n * MIXED_LINF_C * U32 * scale, err.max() / scale
 
 
 def test_mixed_conservation_periodic():

@@ -193,6 +193,26 @@ def test_autotune_single_picks_fastest_and_reports_variants(tmp_path, monkeypatc
     assert cache["single/euler/P3/fp64/lim/N2^20"]["variant"] == 1
 
 
+def test_autotune_single_chooses_between_tile_shapes(tmp_path, monkeypatch):
+    """The default candidates span both wave-tile shapes (64 cells, one per
+    lane: variants 0-3; 128 cells, two per lane: variant 4); the faster one
+    per workload wins and the cache records which shape it is."""
+    import types
+    monkeypatch.setenv("WCC_AUTOTUNE_CACHE", str(tmp_path / "c.json"))
+    fake_torch = types.SimpleNamespace(cuda=types.SimpleNamespace(
+        get_device_properties=lambda i: types.SimpleNamespace(multi_processor_count=256),
+        synchronize=lambda: None))
+    monkeypatch.setitem(__import__("sys").modules, "torch", fake_torch)
+    s = _FakeSolver({(4, 256, 1024): 0.4, (0, 256, 768): 0.45}, {"threads": 256, "blocks": 0, "variant": 1})
+    best = autotune.tune_single(s, None, 0.25, steps=10)
+    assert (best["variant"], best["tile"], best["blocks"]) == (4, "128x2", 1024)
+    assert set(best["per_variant_ms"]) == {0, 1, 2, 3, 4}
+    assert json.load(open(tmp_path / "c.json"))["single/euler/P3/fp64/lim/N2^20"]["tile"] == "128x2"
+    s = _FakeSolver({(4, 256, 1024): 0.5, (0, 256, 768): 0.45}, {"threads": 256, "blocks": 0, "variant": 1})
+    best = autotune.tune_single(s, None, 0.25, steps=10)
+    assert (best["variant"], best["tile"]) == (0, "64x1")
+
+
 def test_autotune_batch_tries_every_schedule(tmp_path, monkeypatch):
     import types
     monkeypatch.setenv("WCC_AUTOTUNE_CACHE", str(tmp_path / "c.json"))
