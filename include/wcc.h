@@ -206,6 +206,40 @@ int wcc_get_launch(const wcc_ctx* ctx, int* threads_per_block, int* blocks, int*
  * WCC_ESTATE (no timed run yet), WCC_EDEVICE. */
 int wcc_last_run_ms(wcc_ctx* ctx, double* ms);
 
+/* ------------------------------------------------------------------------
+ * For callers that cannot allocate device memory or hand over a workspace
+ * (code under HIP graph capture, serving loops that forbid hipMalloc): the
+ * half-steps of wcc_run on a state the caller holds, with the run's scratch
+ * (time-control block and partial wave-speed maxima) in a static device
+ * array of the library instead of the workspace.  The call allocates nothing.
+ *
+ * - state: caller-owned device buffer (256-byte aligned) of at least
+ *   wcc_workspace_bytes - WCC_WORKSPACE_STATE_OFFSET bytes, laid out as the
+ *   part of wcc_bind's workspace that follows its first
+ *   WCC_WORKSPACE_STATE_OFFSET bytes (so a bound workspace + that offset
+ *   works): point-value buffers of parity 0 and 1, then the derivative
+ *   buffers of parity 0 and 1, each nc (and nc*P) rows of ld cells, ld = the
+ *   larger mesh's cell count rounded up to 64, each buffer rounded up to 256
+ *   bytes.  It holds the state of mesh `parity` at time t on entry; after
+ *   half_steps CFL half-steps (as wcc_run: dt = (cfl*dx)/s_max, no end time)
+ *   the state of mesh parity ^ (half_steps & 1) is in that parity's buffers.
+ * - ctx: a created context; only its sizes, parameters and launch shape are
+ *   used (it need not be bound; its own time and state are not touched).
+ * - t_out: NULL, or a host double that receives the time after the steps; a
+ *   non-NULL t_out makes the call synchronise the stream and report
+ *   WCC_ENONFINITE if a step raised a status flag.
+ * - Scratch: WCC_NOALLOC_SCRATCH_BYTES per GPU, held until the process ends;
+ *   a run needs the same amount at any size.  Every call on a GPU shares
+ *   that GPU's array and keeps the last call's contents (each call
+ *   re-initialises what it uses); calls that overlap on one GPU (other
+ *   streams, other threads) race and must be serialised by the caller.
+ * Errors: WCC_EINVAL (NULL or misaligned state, parity, t, cfl, negative
+ * half_steps), WCC_ESIZE (state too small), WCC_EDEVICE, WCC_ENONFINITE. */
+#define WCC_WORKSPACE_STATE_OFFSET 12544
+#define WCC_NOALLOC_SCRATCH_BYTES 16384
+int wcc_run_noalloc(wcc_ctx* ctx, void* state, size_t bytes, int parity, double t, int64_t half_steps, double cfl,
+                    void* hip_stream, double* t_out);
+
 /* Name of a WCC_* code (static string; "unknown error code" otherwise). */
 const char* wcc_strerror(int code);
 /* The last detailed message of a context (owned by the context). */

@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(_HERE, "_lib", "libwcc.so")
 
 WCC_OK, WCC_EINVAL, WCC_ESTATE, WCC_ESIZE, WCC_EDEVICE, WCC_ENONFINITE = 0, -1, -2, -3, -4, -5
 WCC_PMAX = 4
+WCC_WORKSPACE_STATE_OFFSET = 12544   # include/wcc.h
 EQUATIONS = {"advection": 0, "burgers": 1, "euler": 2}
 BCS = {"periodic": 0, "transmissive": 1, "dirichlet": 2}
 PRECISIONS = {"fp64": 0, "fp32_mixed": 1}
@@ -82,6 +83,7 @@ SIGNATURES = {
     "wcc_set_launch": ([_vp, _c.c_int, _c.c_int, _c.c_int], _c.c_int),
     "wcc_get_launch": ([_vp, _c.POINTER(_c.c_int), _c.POINTER(_c.c_int), _c.POINTER(_c.c_int)], _c.c_int),
     "wcc_last_run_ms": ([_vp, _dp], _c.c_int),
+    "wcc_run_noalloc": ([_vp, _vp, _c.c_size_t, _c.c_int, _c.c_double, _i64, _c.c_double, _vp, _dp], _c.c_int),
     "wcc_strerror": ([_c.c_int], _c.c_char_p),
     "wcc_last_error": ([_vp], _c.c_char_p),
     "wcc_destroy": ([_vp], None),

@@ -17,6 +17,7 @@
 #include <cstring>
 #include <limits>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -121,6 +122,20 @@ struct Lay {
 };
 
 Lay bound_lay(const wcc_ctx* c) { return Lay{c->ctrl, c->parts, {c->p[0], c->p[1]}, {c->d[0], c->d[1]}}; }
+
+// The state buffers inside a state region laid out as the workspace after its
+// control block: [p0][p1][d0][d1].
+void state_lay(const wcc_ctx* c, char* q, Lay& L) {
+  const size_t pb = align256((size_t)c->nc * (size_t)c->ld * 8);
+  const size_t db = align256((size_t)c->nc * (size_t)c->P * (size_t)c->ld * c->elem);
+  L.p[0] = reinterpret_cast<double*>(q);
+  q += pb;
+  L.p[1] = reinterpret_cast<double*>(q);
+  q += pb;
+  L.d[0] = q;
+  q += db;
+  L.d[1] = q;
+}
 
 template <class R>
 StepArgs<R> args_at(const wcc_ctx* c, const Lay& L, int parity, int slot, double dt_fixed) {
@@ -257,9 +272,107 @@ int read_ctrl(wcc_ctx* c, Ctrl* h) {
 
 bool check_cfl(double cfl) { return cfl > 0.0 && cfl <= 1.0 && std::isfinite(cfl); }
 
+// ---------------------------------------------------------------------------
+// Static device scratch of wcc_run_noalloc: the time-control block and the
+// partial wave-speed maxima of one run, in a file-scope device array instead
+// of the caller's workspace.  Every GPU the library runs on holds its own copy
+// until the process ends.  Host code never uses the array's name as an
+// address: the device address is looked up once per device with
+// hipGetSymbolAddress (with that device current) and kept per device.
+// ---------------------------------------------------------------------------
+static_assert(256 + wcc::kSmaxPartsBytes == WCC_WORKSPACE_STATE_OFFSET, "state offset of the workspace");
+static_assert(sizeof(Ctrl) <= 256, "control block fits its 256-byte slot");
+static_assert(WCC_WORKSPACE_STATE_OFFSET <= WCC_NOALLOC_SCRATCH_BYTES, "scratch holds control block and parts");
+
+static __device__ __align__(256) unsigned char scratch[WCC_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+char* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of this device's scratch array (device `dev` current).
+int scratch_of(wcc_ctx* c, int dev, char** out) {
+  if (dev < 0 || dev >= kMaxDevices) return fail(c, WCC_EDEVICE, "device %d outside the scratch table", dev);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return fail(c, WCC_EDEVICE, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+    g_scratch_ptr[dev] = static_cast<char*>(ptr);
+  }
+  *out = g_scratch_ptr[dev];
+  return WCC_OK;
+}
+
 }  // namespace
 
 extern "C" {
+
+int wcc_run_noalloc(wcc_ctx* c, void* state, size_t bytes, int parity, double t, int64_t half_steps, double cfl,
+                    void* hip_stream, double* t_out) {
+  if (!c) return WCC_EINVAL;
+  if (!state || ((uintptr_t)state & 255u) != 0) return fail(c, WCC_EINVAL, "state must be a 256-byte aligned device pointer");
+  if ((parity != 0 && parity != 1) || !std::isfinite(t) || half_steps < 0 || !check_cfl(cfl))
+    return fail(c, WCC_EINVAL, "bad parity, time, step count or cfl");
+  size_t ws = 0;
+  wcc_workspace_bytes(c, &ws);
+  const size_t need = ws - WCC_WORKSPACE_STATE_OFFSET;
+  if (bytes < need) return fail(c, WCC_ESIZE, "state region of %zu bytes, need %zu", bytes, need);
+  // the scratch a run needs (control block + partial maxima) does not depend
+  // on the problem size; refuse anything that would not fit the array
+  const size_t scratch_need = WCC_WORKSPACE_STATE_OFFSET;
+  if (scratch_need > WCC_NOALLOC_SCRATCH_BYTES)
+    return fail(c, WCC_ESIZE, "run needs %zu scratch bytes, the static array holds %d", scratch_need,
+                WCC_NOALLOC_SCRATCH_BYTES);
+  int dev = 0;
+  HIPCHK(c, hipGetDevice(&dev));
+  char* sp = nullptr;
+  int rc = scratch_of(c, dev, &sp);
+  if (rc) return rc;
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  Lay L;
+  L.ctrl = reinterpret_cast<Ctrl*>(sp);
+  L.parts = reinterpret_cast<unsigned long long*>(sp + 256);
+  state_lay(c, static_cast<char*>(state), L);
+  // time ring and partial maxima from scratch (they keep the last call's contents)
+  wcc::RingInit init{};
+  init.t = t;
+  init.cfl = cfl;
+  for (int i = 0; i < 3; ++i) {
+    init.ghost[0][i] = c->prm.left_state[i];
+    init.ghost[1][i] = c->prm.right_state[i];
+  }
+  HIPCHK(c, wcc::launch_init_ring(L.ctrl, L.parts, init, s));
+  // wave speed of the input state into slot 0, as wcc_write_dofs does
+  const int64_t n = ncells_of(c, parity);
+  const int blocks = (int)std::min<int64_t>((n + 255) / 256, 4LL * c->cu);
+  hipError_t e;
+  if (c->prm.precision == WCC_FP64) {
+    StepArgs<double> a = args_at<double>(c, L, parity, 0, 0.0);
+    a.n_old = n;
+    e = wcc::launch_state_speed<double>(a, c->eq, c->P, blocks, s);
+  } else {
+    StepArgs<float> a = args_at<float>(c, L, parity, 0, 0.0);
+    a.n_old = n;
+    e = wcc::launch_state_speed<float>(a, c->eq, c->P, blocks, s);
+  }
+  if (e != hipSuccess) return fail(c, WCC_EDEVICE, "speed kernel: %s", hipGetErrorString(e));
+  for (int64_t i = 0; i < half_steps; ++i) {
+    rc = enqueue_step_at(c, L, (int)((parity + i) & 1), (int)(i % 3), 0.0, s);
+    if (rc) return rc;
+  }
+  if (t_out) {
+    Ctrl h;
+    HIPCHK(c, hipMemcpyAsync(&h, L.ctrl, sizeof h, hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    const int slot = (int)(half_steps % 3);
+    *t_out = h.t[slot];
+    if (h.flags[slot] & 3u) return fail(c, WCC_ENONFINITE, "a half-step produced a non-finite value or a "
+                                                          "non-positive density/pressure");
+  }
+  return WCC_OK;
+}
 
 int wcc_params_default(wcc_params* p) {
   if (!p) return WCC_EINVAL;

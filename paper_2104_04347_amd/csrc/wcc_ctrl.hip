@@ -31,4 +31,29 @@ hipError_t launch_batch_set_cfl(Ctrl* ctrl, const BatchInst* inst, int B, CflByD
   return hipGetLastError();
 }
 
+__global__ void k_init_ring(Ctrl* ctrl, unsigned long long* parts, RingInit init) {
+  constexpr int n = (int)(kSmaxPartsBytes / sizeof(unsigned long long));
+  for (int i = threadIdx.x; i < n; i += blockDim.x) parts[i] = 0ull;
+  if (threadIdx.x == 0) {
+    for (int k = 0; k < 3; ++k) {
+      ctrl->t[k] = init.t;
+      ctrl->smax[k] = 0ull;
+      ctrl->flags[k] = 0u;
+    }
+    ctrl->pad0 = 0u;
+    ctrl->t_end = __builtin_inf();
+    ctrl->cfl = init.cfl;
+    ctrl->steps_done = 0;
+    for (int k = 0; k < 5; ++k) ctrl->pad1[k] = 0;
+    for (int side = 0; side < 2; ++side)
+      for (int k = 0; k < 3; ++k) ctrl->ghost[side][k] = init.ghost[side][k];
+    ctrl->pad2[0] = ctrl->pad2[1] = 0.0;
+  }
+}
+
+hipError_t launch_init_ring(Ctrl* ctrl, unsigned long long* parts, RingInit init, hipStream_t s) {
+  hipLaunchKernelGGL(k_init_ring, dim3(1), dim3(256), 0, s, ctrl, parts, init);
+  return hipGetLastError();
+}
+
 }  // namespace wcc

@@ -19,4 +19,15 @@ struct CflByDegree {
 // ctrl[i].cfl = cfl.v[inst[i].P] for the B instances.
 hipError_t launch_batch_set_cfl(Ctrl* ctrl, const BatchInst* inst, int B, CflByDegree cfl, hipStream_t s);
 
+// Initial contents of a time-control block: time t in every slot, no wave
+// speed, no flags, no end time, the CFL number and the Dirichlet ghost states.
+struct RingInit {
+  double t;
+  double cfl;
+  double ghost[2][3];
+};
+// Resets the control block and clears the partial wave-speed maxima
+// (kSmaxPartsBytes at parts); a fill by kernel, no memset node.
+hipError_t launch_init_ring(Ctrl* ctrl, unsigned long long* parts, RingInit init, hipStream_t s);
+
 }  // namespace wcc
