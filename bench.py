@@ -323,6 +323,7 @@ def time_2d(args):
              "cfl": cfl, "half_steps": args.steps2d, "kernel": kernel, "launch": launch, "launch_us": launch_s * 1e6,
              "bytes_per_launch": bpl, "hbm_frac": bpl / launch_s / HBM_PEAK,
              "traffic": measured_traffic(rec_key, N, "2d"), "traffic_key": rec_key,
+             "issue_roof": issue_roof(rec_key, N, launch_s, "2d"),
              "valid": bool((info.flags & 3) == 0)}
         s.close()
         if not args.no_cpu:
