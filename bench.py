@@ -293,7 +293,9 @@ def time_2d(args):
             c = autotune.cached_2d(s) if args.tune == "auto" else None
             if c is None:
                 c = autotune.tune_2d(s, q0, cfl)
-                launch = {k: c[k] for k in ("variant", "threads", "blocks")} | {"source": "autotuned"}
+                launch = {k: c[k] for k in ("variant", "threads", "blocks")} | {
+                    "source": "autotuned",
+                    "best_us_per_variant": {str(v): round(ms * 1e3, 2) for v, ms in c["per_variant_ms"].items()}}
             else:
                 launch = {k: c[k] for k in ("variant", "threads", "blocks")} | {"source": "autotune cache"}
             s.set_launch(launch["threads"], launch["blocks"], launch["variant"])

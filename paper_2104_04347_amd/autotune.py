@@ -179,9 +179,10 @@ def cached_2d(solver: "binding.Solver2D"):
 
 
 def tune_2d(solver: "binding.Solver2D", q0: np.ndarray, cfl: float, steps: int = 96, threads=(128, 256),
-            block_factors=(0, 0.5, 1, 2, 3, 4), variants=(1, 2), verbose: bool = False) -> dict:
+            block_factors=(0, 0.5, 1, 2, 3, 4), variants=(1, 2, 3), verbose: bool = False) -> dict:
     """Time 2D launch shapes on `solver` (state q0): row-marching variant
-    (1 without, 2 with the next row prefetched) x threads per block x blocks
+    (1 without, 2 with the next row prefetched, 3 as 2 with band-major work
+    items) x threads per block x blocks
     per launch (block factor x compute units; 0 = the library's default,
     which fills the device at the kernel's occupancy).  Longer runs per wave
     re-expand fewer priming rows, more waves hide more latency; the best
@@ -207,5 +208,6 @@ def tune_2d(solver: "binding.Solver2D", q0: np.ndarray, cfl: float, steps: int =
     c[key_2d(solver)] = {k: best[k] for k in ("variant", "threads", "blocks", "ms_per_step")}
     _save_cache(c)
     solver.set_launch(best["threads"], best["blocks"], best["variant"])
+    best["per_variant_ms"] = {v: min(r["ms_per_step"] for r in results if r["variant"] == v) for v in variants}
     best["tried"] = results
     return best

@@ -49,7 +49,8 @@ struct wcc2d_ctx {
   int parity_w = 0;
   int64_t launched = 0, steps = 0;
   int threads = 256, blocks = 0, cu = 0;
-  int variant = 2;   // 0: 8 x 8 wave tiles, 1: row marching over 64-column strips, 2: the same with prefetch
+  int variant = 2;   // 0: 8 x 8 wave tiles, 1: row marching over 64-column strips, 2: the same with prefetch,
+                     // 3: as 2 with band-major work items (neighbouring strips on one CU / XCD)
   hipStream_t capture = nullptr;
   hipGraphExec_t graphs[6] = {};
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -474,7 +475,7 @@ int wcc2d_get_launch(wcc2d_ctx* c, int* threads_per_block, int* blocks, int* var
 
 int wcc2d_set_launch(wcc2d_ctx* c, int threads_per_block, int blocks, int variant) {
   if (!c) return WCC_EINVAL;
-  if (variant < -1 || variant > 2) return fail2(c, WCC_EINVAL, "variant must be -1 (keep), 0, 1 or 2");
+  if (variant < -1 || variant > 3) return fail2(c, WCC_EINVAL, "variant must be -1 (keep), 0, 1, 2 or 3");
   if (threads_per_block != 0 && (threads_per_block % 64 != 0 || threads_per_block < 64 || threads_per_block > 256))
     return fail2(c, WCC_EINVAL, "threads per block must be 64, 128, 192 or 256");
   if (blocks < 0) return fail2(c, WCC_EINVAL, "negative block count");

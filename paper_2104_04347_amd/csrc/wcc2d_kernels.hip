@@ -231,7 +231,16 @@ __device__ __forceinline__ void put_carry(RowCarry<EQ, P>& carry, int c, int lan
 
 // PF: load the next unit's upper row before expanding the current one (one
 // row of state in flight per wave, at the cost of its registers).
-template <int EQ, int P, bool LIM, bool PF>
+// BANDS: band-major work items.  A strip's 64-cell row pieces start every 63
+// cells, so each piece shares its edge cache lines with the neighbouring
+// strips' pieces; with BANDS the waves of a block take neighbouring strips
+// over the same band of rows (they load the shared lines at about the same
+// time, through the same L2), and the blocks of one XCD (the hardware places
+// block b on XCD b mod 8) take consecutive items.  Each wave owns one strip
+// over one band of rows: no run crosses a strip.  Without BANDS (or with
+// fewer waves than strips) the waves split the strip-major (strip, row)
+// units evenly.  The arithmetic of every unit is the same either way.
+template <int EQ, int P, bool LIM, bool PF, bool BANDS>
 __global__ __launch_bounds__(256) void k2d_half_step_rows(const Step2Args a) {
   constexpr int NC = ncomp<EQ>(), NV = nvert(P), ND = ndof(P);
   __shared__ RowCarry<EQ, P> carry_all[4];
@@ -241,7 +250,19 @@ __global__ __launch_bounds__(256) void k2d_half_step_rows(const Step2Args a) {
   const int strips = (a.nxn + 62) / 63, rows = a.nyn;
   const int64_t units = (int64_t)strips * rows, waves = (int64_t)gridDim.x * nw;
   const int64_t gw = (int64_t)blockIdx.x * nw + wave;
-  const int u_begin = (int)(gw * units / waves), u_end = (int)((gw + 1) * units / waves);
+  int u_begin = (int)(gw * units / waves), u_end = (int)((gw + 1) * units / waves);
+  if (BANDS && waves >= strips) {
+    const int G = (int)gridDim.x;
+    const int lb = (G & 7) == 0 ? (int)(blockIdx.x & 7) * (G >> 3) + (int)(blockIdx.x >> 3) : (int)blockIdx.x;
+    const int64_t item = (int64_t)lb * nw + wave;
+    const int bands = (int)(waves / strips);
+    u_begin = u_end = 0;
+    if (item < (int64_t)bands * strips) {
+      const int band = (int)(item / strips), sx = (int)(item - (int64_t)band * strips);
+      u_begin = sx * rows + (int)((int64_t)band * rows / bands);
+      u_end = sx * rows + (int)((int64_t)(band + 1) * rows / bands);
+    }
+  }
   double dt;
   if (!wcc::step_time(a.ctrl, a.parts, a.slot, 1.0, a.dt_fixed, blockIdx.x == 0 && threadIdx.x < 64, dt)) return;
   const double lamx = dt / a.dx, lamy = dt / a.dy;
@@ -342,10 +363,12 @@ __global__ __launch_bounds__(256) void k2d_state_speed(const Step2Args a) {
 
 template <int EQ, int P, bool LIM>
 static hipError_t launch_epl(const Step2Args& a, int variant, int blocks, int threads, hipStream_t s) {
-  if (variant == 2)
-    hipLaunchKernelGGL((k2d_half_step_rows<EQ, P, LIM, true>), dim3(blocks), dim3(threads), 0, s, a);
+  if (variant == 3)
+    hipLaunchKernelGGL((k2d_half_step_rows<EQ, P, LIM, true, true>), dim3(blocks), dim3(threads), 0, s, a);
+  else if (variant == 2)
+    hipLaunchKernelGGL((k2d_half_step_rows<EQ, P, LIM, true, false>), dim3(blocks), dim3(threads), 0, s, a);
   else if (variant == 1)
-    hipLaunchKernelGGL((k2d_half_step_rows<EQ, P, LIM, false>), dim3(blocks), dim3(threads), 0, s, a);
+    hipLaunchKernelGGL((k2d_half_step_rows<EQ, P, LIM, false, false>), dim3(blocks), dim3(threads), 0, s, a);
   else
     hipLaunchKernelGGL((k2d_half_step<EQ, P, LIM>), dim3(blocks), dim3(threads), 0, s, a);
   return hipGetLastError();
@@ -402,10 +425,15 @@ hipError_t launch_state_speed2(const Step2Args& a, int eq, int P, int blocks, hi
 
 template <int EQ, int P, bool LIM>
 static hipError_t occ_epl(int variant, int threads, int* per_cu) {
+  if (variant == 3)
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k2d_half_step_rows<EQ, P, LIM, true, true>, threads,
+                                                        0);
   if (variant == 2)
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k2d_half_step_rows<EQ, P, LIM, true>, threads, 0);
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k2d_half_step_rows<EQ, P, LIM, true, false>, threads,
+                                                        0);
   if (variant == 1)
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k2d_half_step_rows<EQ, P, LIM, false>, threads, 0);
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k2d_half_step_rows<EQ, P, LIM, false, false>,
+                                                        threads, 0);
   return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k2d_half_step<EQ, P, LIM>, threads, 0);
 }
 

@@ -54,7 +54,9 @@ def modes_state(P, Nx, Ny, seed=3):
     return inputs.taylor2d(fn, P, Nx, Ny)
 
 
-VARIANTS = [0, 1, 2]   # 8 x 8 wave tiles; row marching over 64-column strips, without and with prefetch
+# 8 x 8 wave tiles; row marching over 64-column strips, without and with
+# prefetch; with prefetch and band-major work items
+VARIANTS = [0, 1, 2, 3]
 
 
 @pytest.mark.parametrize("variant", VARIANTS)
@@ -79,8 +81,8 @@ def test_small_meshes_bitwise(Nx, Ny, variant):
     assert_bitwise(q, info, r, f"Nx={Nx} Ny={Ny} variant={variant}")
 
 
-@pytest.mark.parametrize("variant", [1, 2])
-@pytest.mark.parametrize("threads,blocks", [(64, 1), (64, 3), (128, 7), (256, 2), (192, 0)])
+@pytest.mark.parametrize("variant", [1, 2, 3])
+@pytest.mark.parametrize("threads,blocks", [(64, 1), (64, 3), (128, 7), (256, 2), (192, 0), (256, 8), (64, 16)])
 def test_strip_launch_shapes_bitwise(threads, blocks, variant):
     """Row marching: runs of (strip, row) units split over 1 to 28 waves,
     starting and ending inside strips, on a mesh of three ragged strips."""

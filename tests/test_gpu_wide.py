@@ -93,7 +93,7 @@ def test_wide_c3_full_size(P, shape):
 
 
 def test_wide_long_run_graphs():
-    """100 half-steps (two 48-step graphs and a 4-step remainder graph) equal
+    """100 half-steps (two 48-step graphs and 4 single launches) equal
     100 single wcc_step calls and the oracle."""
     P, N = 3, 3001
     q0, _ = inputs.euler_riemann(5, P, N)
