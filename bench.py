@@ -119,6 +119,9 @@ def launch_shape_single(args, s, q0, cfl=None, **tune_kw) -> dict:
     when there is one (and --tune is not 'force'), else tune now (--tune off:
     the library's default).  Results do not depend on the shape."""
     from paper_2104_04347_amd import autotune
+    if getattr(args, "c3_variant", -1) >= 0 and cfl is None:
+        s.set_launch(256, 0, args.c3_variant)
+        return {**s.get_launch(), "tile": autotune.TILE_SHAPE[args.c3_variant], "source": "--c3-variant"}
     if args.tune == "off":
         return {**s.get_launch(), "source": "library default"}
     if args.tune == "auto" and autotune.apply_single(s):
@@ -314,8 +317,8 @@ def time_2d(args):
         cells = N * N if bc == "periodic" else 0.5 * ((N + 1) ** 2 + N * N)
         dofs = cells * nc * nd * args.steps2d
         bpl = 2.0 * cells * nc * nd * 8
-        kernel = (f"k2d_half_step_rows<{eq},P={P},{'limiter' if lim else 'no limiter'},"
-                  f"{'prefetch' if launch['variant'] == 2 else 'no prefetch'}>")
+        form = {1: "no prefetch", 2: "prefetch", 3: "prefetch,bands"}.get(launch["variant"], "8x8 tiles")
+        kernel = f"k2d_half_step_rows<{eq},P={P},{'limiter' if lim else 'no limiter'},{form}>"
         # the counter record belongs to the kernel, the mesh and the launch
         # grid (the grid sets how many priming rows are re-read)
         eff = s.get_launch()                   # the grid actually launched (0 resolved)
@@ -524,6 +527,8 @@ def main():
     ap.add_argument("--large-steps", type=int, default=10000)
     ap.add_argument("--large-variant", type=int, default=-1, choices=(-1, 0, 1, 2, 3),
                     help="launch variant of the large workload (256 threads, default grid); -1: per --tune")
+    ap.add_argument("--c3-variant", type=int, default=-1, choices=(-1, 0, 1, 2, 3, 4),
+                    help="pin the launch variant of the N=2^20 legs (256 threads, default grid; counter passes)")
     ap.add_argument("--tune", choices=("auto", "force", "off"), default="auto",
                     help="launch shapes: cached autotuner result else tune (auto), always tune, or library default")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
