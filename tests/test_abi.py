@@ -154,7 +154,7 @@ def test_2d_create_validates():
     assert lib.wcc2d_step(h, ctypes.c_double(0.25), ctypes.c_double(0.0)) == binding.WCC_ESTATE
     assert lib.wcc2d_bind(h, ctypes.c_void_p(256), 16, None) == binding.WCC_ESIZE
     assert lib.wcc2d_set_launch(h, 100, 0, -1) == binding.WCC_EINVAL
-    assert lib.wcc2d_set_launch(h, 0, 0, 3) == binding.WCC_EINVAL
+    assert lib.wcc2d_set_launch(h, 0, 0, 4) == binding.WCC_EINVAL
     assert lib.wcc2d_set_launch(h, 128, 0, 0) == 0
     t, b, v = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
     assert lib.wcc2d_get_launch(h, ctypes.byref(t), ctypes.byref(b), ctypes.byref(v)) == 0
