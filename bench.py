@@ -503,6 +503,7 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-p2", action="store_true", help="skip the P = 2 legs of the benchmark workload")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--batch-B", type=int, default=4096)
     ap.add_argument("--batch-steps", type=int, default=100)
@@ -572,6 +573,25 @@ def main():
         print(f"[bench] seed {sd}: fp64 {e['fp64']:.3e} DOF/s", file=sys.stderr, flush=True)
     if seeds_out:
         seeds_out[str(args.seed)] = {"fp64": r64["value"], **({"fp32_mixed": rmx["value"]} if rmx else {})}
+    # the same workload at P = 2 (CFL 0.3 per half-step), both precisions
+    rp2 = None
+    if not args.no_p2:
+        import copy
+        a2 = copy.copy(args)
+        a2.P, a2.cfl, a2.c3_variant = 2, 0.3, -1
+        q2, _ = inputs.euler_riemann(args.seed, 2, args.N)
+        rp2 = {}
+        for prec in ("fp64",) + (() if args.no_mixed else ("fp32_mixed",)):
+            r = time_single(a2, prec, q2)
+            bpl = bytes_per_launch(args.N, 2, 3, prec)
+            ls = r["lib_event_ms"] / 1e3 / args.steps
+            rp2[prec] = {"value": r["value"], "unit": "cell-DOF updates/s", "ms_per_step": r["wall_s"] * 1e3 / args.steps,
+                         "launch_us": round(ls * 1e6, 2), "bytes_per_launch": bpl,
+                         "hbm_frac": round(bpl / ls / HBM_PEAK, 4), "mall_resident": bool(bpl <= MALL_BYTES),
+                         "valid": bool(r["ok"]), "launch": r["launch"]}
+            print(f"[bench] P=2 {prec}: {r['value']:.3e} DOF/s", file=sys.stderr, flush=True)
+        del q2
+
     rb = None
     if not args.no_batch:
         rb = time_batch(args)
@@ -669,6 +689,8 @@ def main():
                               "gbs": round(rm["gbs"], 1), "tflops": round(rm["tflops"], 3),
                               "issue_roof": issue_roof(mkey, args.N, rm["launch_us"] / 1e6, msrc),
                               "vs_fp64": rmx["vs_fp64"], "launch": rmx["launch"]}
+    if rp2 is not None:
+        line["P2"] = {"config": f"the same workload at P = 2, CFL 0.3 per half-step", **rp2}
     if rb is not None:
         line["batched"] = rb
     if r2 is not None:
