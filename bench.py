@@ -289,9 +289,10 @@ def time_2d(args):
         bc = "transmissive" if name.startswith("riemann") else "periodic"
         s = binding.Solver2D(eq, P, N, N, limiter=lim, x_left=dom[0], x_right=dom[1], y_left=dom[2], y_right=dom[3],
                              bc=bc)
-        # launch shape: the library's default (row marching with prefetch, 256
-        # threads, device-filling grid), a cached autotuner result, or tune now
-        launch = {"variant": 2, "threads": 256, "blocks": 0, "source": "library default"}
+        # launch shape: the library's default (row marching with prefetch and
+        # band-major work items, 256 threads, device-filling grid), a cached
+        # autotuner result, or tune now
+        launch = {"variant": 3, "threads": 256, "blocks": 0, "source": "library default"}
         if args.tune != "off":
             c = autotune.cached_2d(s) if args.tune == "auto" else None
             if c is None:

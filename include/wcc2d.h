@@ -142,11 +142,11 @@ int wcc2d_totals(wcc2d_ctx* c, double* per_component);
  * blocks per launch (0 = resident capacity) and the work decomposition
  * (variant 0: every wavefront expands 8 x 8 old-cell tiles and produces their
  * 7 x 7 new cells; 1: wavefronts walk 64-column strips upward one row at a
- * time, expanding every old cell once per strip; 2, the default: as 1, with
- * the next row's loads issued before the current row is expanded; 3: as 2,
- * with each wave owning one strip over one band of rows and the waves of a
- * block (and the blocks of one XCD) taking neighbouring strips, so that the
- * cache lines neighbouring strips share are fetched once; -1 keeps the
+ * time, expanding every old cell once per strip; 2: as 1, with the next
+ * row's loads issued before the current row is expanded; 3, the default: as
+ * 2, with each wave owning one strip over one band of rows and the waves of
+ * a block (and the blocks of one XCD) taking neighbouring strips, so that
+ * the cache lines neighbouring strips share are fetched once; -1 keeps the
  * current one).  Results do not depend on it.  Errors: WCC_EINVAL. */
 int wcc2d_set_launch(wcc2d_ctx* c, int threads_per_block, int blocks, int variant);
 

@@ -49,8 +49,8 @@ struct wcc2d_ctx {
   int parity_w = 0;
   int64_t launched = 0, steps = 0;
   int threads = 256, blocks = 0, cu = 0;
-  int variant = 2;   // 0: 8 x 8 wave tiles, 1: row marching over 64-column strips, 2: the same with prefetch,
-                     // 3: as 2 with band-major work items (neighbouring strips on one CU / XCD)
+  int variant = 3;   // 0: 8 x 8 wave tiles, 1: row marching over 64-column strips, 2: the same with prefetch,
+                     // 3 (default): as 2 with band-major work items (neighbouring strips on one CU / XCD)
   hipStream_t capture = nullptr;
   hipGraphExec_t graphs[6] = {};
   hipEvent_t ev0 = nullptr, ev1 = nullptr;

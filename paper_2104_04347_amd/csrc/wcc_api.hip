@@ -62,6 +62,7 @@ struct wcc_ctx {
   int64_t launched = 0;     // kernels enqueued since the write (slot = launched % 3)
   int64_t steps = 0;        // half-steps known to be done (exact after a sync)
   int threads = 256, blocks = 0;
+  int default_blocks = 0;    // device-filling grid of the current shape (0: not computed yet)
   int prefetch = 1;          // kernel variant bits: 1 = prefetch the next tile's inputs, 2 = aligned stores
   int cu = 0;
   hipStream_t capture = nullptr;
@@ -168,6 +169,9 @@ StepArgs<R> args_for(const wcc_ctx* c, int parity, int slot, double dt_fixed) {
 
 int blocks_for(wcc_ctx* c) {
   if (c->blocks > 0) return c->blocks;
+  // the device-filling grid of the current shape, computed once (the
+  // occupancy query costs host time on every launch otherwise)
+  if (c->default_blocks > 0) return c->default_blocks;
   const bool wide = c->prefetch == kWideVariant;
   const int64_t span = wide ? 127 : 63;   // new cells per wave tile
   const int64_t tiles = (std::max(ncells_of(c, 0), ncells_of(c, 1)) + span - 1) / span;
@@ -185,7 +189,8 @@ int blocks_for(wcc_ctx* c) {
   if (e != hipSuccess || per_cu < 1) per_cu = 1;
   int64_t full = (int64_t)per_cu * c->cu;
   int64_t need = (tiles + waves - 1) / waves;
-  return (int)std::max<int64_t>(1, std::min(full, need));
+  c->default_blocks = (int)std::max<int64_t>(1, std::min(full, need));
+  return c->default_blocks;
 }
 
 // Enqueue one half-step kernel on the buffers of L: launch number `launched`
@@ -752,12 +757,16 @@ int wcc_get_launch(const wcc_ctx* c, int* threads_per_block, int* blocks, int* v
 int wcc_set_launch(wcc_ctx* c, int threads_per_block, int blocks, int variant) {
   if (!c) return WCC_EINVAL;
   if (variant < -1 || variant > kWideVariant) return fail(c, WCC_EINVAL, "variant must be -1 (keep) or 0..4");
-  if (variant >= 0) c->prefetch = variant;
+  if (variant >= 0) {
+    c->prefetch = variant;
+    c->default_blocks = 0;
+  }
   if (threads_per_block != 0 && (threads_per_block % 64 != 0 || threads_per_block < 64 || threads_per_block > 256))
     return fail(c, WCC_EINVAL, "threads per block must be 64, 128, 192 or 256");
   if (blocks < 0) return fail(c, WCC_EINVAL, "negative block count");
   c->threads = threads_per_block ? threads_per_block : 256;
   c->blocks = blocks;
+  c->default_blocks = 0;
   drop_graphs(c);
   return WCC_OK;
 }

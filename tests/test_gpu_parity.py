@@ -437,3 +437,49 @@ def test_context_managers_release_the_workspace():
     with binding.Solver2D("burgers", 1, 8, 8, limiter=True) as s2:
         pass
     assert s2.h is None and s2.workspace is None
+
+
+def test_degenerate_calls():
+    """Zero half-steps leave the state, time and parity as written; an
+    advance to the current time takes no step; the smallest mesh (N = 2)
+    runs in every boundary condition."""
+    P, N = 2, 300
+    q0, _ = inputs.euler_riemann(6, P, N)
+    s = binding.Solver("euler", P, N, "transmissive", limiter=True)
+    s.write(q0, t=0.125)
+    s.run(0, 0.25)
+    q, info = s.read()
+    assert np.array_equal(q, q0) and info.t == 0.125 and info.parity == 0 and info.half_steps == 0
+    assert s.advance(0.125, 0.25) == 0
+    q, info = s.read()
+    assert np.array_equal(q, q0) and info.t == 0.125
+    s.close()
+    for bc in ("periodic", "transmissive", "dirichlet"):
+        kw = dict(x_left=0.0, x_right=2.0)
+        n0 = 2 if bc == "periodic" else 3
+        q0 = np.full((1, 2, n0), 0.4)
+        q0[0, 1] = 0.0
+        kw.update(left_state=(0.4, 0, 0), right_state=(0.4, 0, 0))
+        q, info, taken = gpu_run("burgers", 1, 2, bc, q0, limiter=True, steps=5, cfl=0.3, **kw)
+        ref = oracle_run("burgers", 1, 2, bc, q0, limiter=True, steps=5, cfl=0.3, **kw)
+        assert_bitwise(q, info, taken, ref, f"N=2 {bc}")
+
+
+def test_batch_single_instance_and_degree_zero():
+    """A batch of one instance, and instances of degree 0, equal
+    single-instance runs bit for bit."""
+    for P_list, N_list in (([3], [1000]), ([0, 1, 0], [300, 65, 2])):
+        P = np.array(P_list, dtype=np.int32)
+        N = np.array(N_list, dtype=np.int64)
+        bt = binding.Batch("euler", P, N, "transmissive", limiter=True, precision="fp64")
+        qs = [inputs.euler_riemann(10 + b, int(P[b]), int(N[b]))[0] for b in range(P.size)]
+        for b in range(P.size):
+            bt.write(b, qs[b])
+        bt.prepare()
+        bt.advance(13, [0.4, 0.4, 0.3, 0.25, 0.25])
+        for b in range(P.size):
+            qb, ib = bt.read(b)
+            q, info, _ = gpu_run("euler", int(P[b]), int(N[b]), "transmissive", qs[b], limiter=True, steps=13,
+                                 cfl=[0.4, 0.4, 0.3, 0.25, 0.25][int(P[b])])
+            assert ib.t == info.t and np.array_equal(qb, q), (P_list, b)
+        bt.close()
