@@ -21,12 +21,15 @@ from paper_2104_04347_amd import inputs
 
 from test_oracle_linear import _mat, oracle_matrices
 import test_oracle_boundary_speed as tbs
+import test_oracle_euler_limiter as tel
 
 import json
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
 MUTANTS = {
+    "characteristic vertex operand": ("mat3(e.L, vl, cl);", "mat3(e.L, vr, cl);"),
+    "back-projection matrix": ("mat3(e.Rm, cd[k], y);", "mat3(e.L, cd[k], y);"),
     "derivative correction sign": ("NCO[k] = (k % 2 == 1) ? -(2.0", "NCO[k] = (k % 2 == 1) ? (2.0"),
     "left half-average sign": ("SCA[k] = (k % 2 == 0) ? CA[k] : -CA[k];", "SCA[k] = CA[k];"),
     "CK factor (k+1)/m": ("CKR[k][m] = (m > 0) ? (double)(k + 1) / (double)m", "CKR[k][m] = (m > 0) ? (double)(k + 1) / (double)(m + 1)"),
@@ -163,7 +166,12 @@ def quick_pins() -> list:
     def dirichlet_appendix():
         return all(tbs.dirichlet_end_cells_match_appendix(P, 0.2371) < 4e-15 for P in (1, 2, 3))
 
+    def euler_limiter():
+        worst, acted = tel.euler_limiter_deviation(2, 96, steps=6)
+        return worst <= tel.TOL[2] and acted >= 5
+
     check("appendix A", appendix)
+    check("Euler characteristic limiter", euler_limiter)
     check("Dirichlet ghosts", dirichlet_ends)
     check("wave speed", tbs.wave_speed_time_steps_ok)
     check("limiter brute force", limiter_brute)
