@@ -125,7 +125,8 @@ int blocks_for(wcc2d_ctx* c, int parity) {
   const int64_t units = c->variant >= 1 ? ((nx + 62) / 63) * ny : ((nx + 6) / 7) * ((ny + 6) / 7);
   const int waves = c->threads / 64;
   int per_cu = 0;
-  if (wcc2d::occupancy_half_step2(c->eq, c->P, c->prm.limiter != 0, c->variant, c->threads, &per_cu) != hipSuccess ||
+  if (wcc2d::occupancy_half_step2(c->eq, c->P, c->prm.limiter != 0, c->variant, c->threads, c->plane, &per_cu) !=
+          hipSuccess ||
       per_cu < 1)
     per_cu = 1;
   const int64_t full = (int64_t)per_cu * c->cu, need = (units + waves - 1) / waves;

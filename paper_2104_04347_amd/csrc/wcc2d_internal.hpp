@@ -30,10 +30,13 @@ struct Step2Args {
 };
 
 // variant 0: 8 x 8 wave tiles; 1: row marching over 64-column strips; 2: the
-// same with the next row prefetched (identical results)
+// same with the next row prefetched; 3: the same with band-major work items
+// (identical results)
 hipError_t launch_half_step2(const Step2Args& a, int eq, int P, bool lim, int variant, int blocks, int threads,
                              hipStream_t s);
 hipError_t launch_state_speed2(const Step2Args& a, int eq, int P, int blocks, hipStream_t s);
-hipError_t occupancy_half_step2(int eq, int P, bool lim, int variant, int threads, int* blocks_per_cu);
+// plane: doubles per plane of the state (selects the kernel form launched for it)
+hipError_t occupancy_half_step2(int eq, int P, bool lim, int variant, int threads, int64_t plane,
+                                int* blocks_per_cu);
 
 }  // namespace wcc2d

@@ -57,29 +57,85 @@ __device__ __forceinline__ void combine(Par2<P>& g, double A_RU, double B_RD, do
   g.gy = (A_gR - B_gR) + (C_gL - E_gL);
 }
 
-template <int EQ, int P>
+// ---- buffer addressing of the state (row-marching kernels) -----------------
+// A row kernel loads and stores nc * ndof planes per mesh row (40 for Euler at
+// P = 3).  With a 64-bit base pointer per plane the row loop needs a scalar
+// register pair per plane for the loads and another for the stores -- more
+// than the scalar register file holds, so the spilled pointers are reloaded
+// from vector lanes on every row.  Buffer instructions take one resource per
+// state buffer, a per-lane 32-bit offset (the cell and the component's group
+// of planes) and a scalar 32-bit offset (the plane of the degree of freedom
+// within the group): ndof - 1 scalar offsets, shared by loads and stores.
+// Every offset is 32-bit, so this form serves state buffers below 2 GiB
+// (`buffer_form`); larger states take the pointer form.
+typedef unsigned int u32x2 __attribute__((__vector_size__(2 * sizeof(unsigned int))));
+
+__host__ __device__ constexpr bool buffer_form(int64_t doubles_per_buffer) {
+  return doubles_per_buffer * 8 < ((int64_t)1 << 31);
+}
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t state_rsrc(const double* p) {
+  // raw buffer (stride 0) with 2^31 - 1 bytes of range; word 3 as for
+  // untyped dword accesses on gfx9-family parts
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(p), (short)0, 0x7fffffff, 0x00020000);
+}
+
+// Per-lane byte offset of the first plane of a group at `cell`, kept opaque so
+// that the compiler does not fold the uniform part into one scalar offset per
+// plane again.
+__device__ __forceinline__ uint32_t group_offset(uint32_t cell, int group, uint32_t plane_bytes) {
+  uint32_t v = cell * 8u + (uint32_t)group * plane_bytes;
+  asm("" : "+v"(v));
+  return v;
+}
+
+__device__ __forceinline__ double buf_load(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, 0));
+}
+
+__device__ __forceinline__ void buf_store(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff, double x) {
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, x), r, (int)voff, (int)soff, 0);
+}
+
+// Store the new cell's DOFs of component c (point value, then u_{kx,ly} in
+// DOF order) and flag non-finite values.
+template <int EQ, int P, bool BUF>
 __device__ __forceinline__ void store_cell(const Step2Args& a, int c, uint32_t ncell, double pv,
                                            const double (&D)[P + 1][P + 1], unsigned& flags) {
   constexpr int ND = ndof(P);
   bool ok = __builtin_isfinite(pv);
-  wcc::row_store(wcc::row_base(a.q_new + (int64_t)(c * ND) * a.plane), ncell, pv);
+  if constexpr (BUF) {
+    const __amdgpu_buffer_rsrc_t r = state_rsrc(a.q_new);
+    const uint32_t pb = (uint32_t)a.plane * 8u, vo = group_offset(ncell, c * ND, pb);
+    buf_store(r, vo, 0u, pv);
 #pragma unroll
-  for (int n = 1; n <= P; ++n)
+    for (int n = 1; n <= P; ++n)
 #pragma unroll
-    for (int l = 0; l <= n; ++l) {
-      const double x = D[n - l][l];
-      ok = ok && __builtin_isfinite(x);
-      wcc::row_store(wcc::row_base(a.q_new + (int64_t)(c * ND + dof(n - l, l)) * a.plane), ncell, x);
-    }
+      for (int l = 0; l <= n; ++l) {
+        const double x = D[n - l][l];
+        ok = ok && __builtin_isfinite(x);
+        buf_store(r, vo, (uint32_t)dof(n - l, l) * pb, x);
+      }
+  } else {
+    wcc::row_store(wcc::row_base(a.q_new + (int64_t)(c * ND) * a.plane), ncell, pv);
+#pragma unroll
+    for (int n = 1; n <= P; ++n)
+#pragma unroll
+      for (int l = 0; l <= n; ++l) {
+        const double x = D[n - l][l];
+        ok = ok && __builtin_isfinite(x);
+        wcc::row_store(wcc::row_base(a.q_new + (int64_t)(c * ND + dof(n - l, l)) * a.plane), ncell, x);
+      }
+  }
   if (!ok) flags |= 1u;
 }
 
 // New cell of this lane from its parents' data (gather(c, g) fills Par2 for
 // component c): average (Eq. 2DIntegral), derivatives (Eq. 2DDerivatives),
 // limiter (Section 3.2; characteristic fields for Euler, Section 4), point
-// value, store, wave-speed rate.
-template <int EQ, int P, bool LIM, class Gather>
-__device__ __forceinline__ void new_cell2(const Step2Args& a, Gather&& gather, bool mine, uint32_t ncell, double hx,
+// value, store (store(c, point value, D, flags)), wave-speed rate.
+template <int EQ, int P, bool LIM, class Gather, class Store>
+__device__ __forceinline__ void new_cell2(const Step2Args& a, Gather&& gather, Store&& store, bool mine, double hx,
                                           double hy, double& smax, unsigned& flags) {
   constexpr int NC = ncomp<EQ>();
   double ab[NC];
@@ -101,7 +157,7 @@ __device__ __forceinline__ void new_cell2(const Step2Args& a, Gather&& gather, b
     char_limit2d<P>(a.ph, a.dx, a.dy, ab, D, vx);
     if (mine) {
 #pragma unroll
-      for (int c = 0; c < 4; ++c) store_cell<EQ, P>(a, c, ncell, point_value<P>(ab[c], D[c]), D[c], flags);
+      for (int c = 0; c < 4; ++c) store(c, point_value<P>(ab[c], D[c]), D[c], flags);
     }
   } else {
 #pragma unroll
@@ -114,7 +170,7 @@ __device__ __forceinline__ void new_cell2(const Step2Args& a, Gather&& gather, b
       if constexpr (P >= 1) new_derivatives<P>(g.VA, g.VB, g.VC, g.VE, D);
       if constexpr (LIM && P >= 1) limit2d<P>(a.ph.eps, abar, D, g.VA[0], g.VC[0], g.VE[0], g.VB[0]);
       const double pv = point_value<P>(abar, D);
-      if (mine) store_cell<EQ, P>(a, c, ncell, pv, D, flags);
+      if (mine) store(c, pv, D, flags);
     }
   }
   if (mine) {
@@ -125,21 +181,33 @@ __device__ __forceinline__ void new_cell2(const Step2Args& a, Gather&& gather, b
 }
 
 // Load the state of the old cell (i, j) of this lane.
-template <int EQ, int P>
+template <int EQ, int P, bool BUF = false>
 __device__ __forceinline__ void load_old(const Step2Args& a, int i, int j, double (&q)[ncomp<EQ>()][ndof(P)]) {
   constexpr int NC = ncomp<EQ>(), ND = ndof(P);
   const uint32_t cell = (uint32_t)(j * a.nxo + i);
+  if constexpr (BUF) {
+    const __amdgpu_buffer_rsrc_t r = state_rsrc(a.q_old);
+    const uint32_t pb = (uint32_t)a.plane * 8u;
 #pragma unroll
-  for (int c = 0; c < NC; ++c)
+    for (int c = 0; c < NC; ++c) {
+      const uint32_t vo = group_offset(cell, c * ND, pb);
 #pragma unroll
-    for (int d = 0; d < ND; ++d) q[c][d] = wcc::row_at(wcc::row_base(a.q_old + (int64_t)(c * ND + d) * a.plane), cell);
+      for (int d = 0; d < ND; ++d) q[c][d] = buf_load(r, vo, (uint32_t)d * pb);
+    }
+  } else {
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+#pragma unroll
+      for (int d = 0; d < ND; ++d)
+        q[c][d] = wcc::row_at(wcc::row_base(a.q_old + (int64_t)(c * ND + d) * a.plane), cell);
+  }
 }
 
 // Load and expand the old cell (i, j) of this lane.
-template <int EQ, int P>
+template <int EQ, int P, bool BUF = false>
 __device__ __forceinline__ void old_of(const Step2Args& a, int i, int j, double nlx, double nly, Old2<EQ, P>& o) {
   double q[ncomp<EQ>()][ndof(P)];
-  load_old<EQ, P>(a, i, j, q);
+  load_old<EQ, P, BUF>(a, i, j, q);
   old_cell2<EQ, P>(q, nlx, nly, a.ph, o);
 }
 
@@ -177,7 +245,11 @@ __device__ __forceinline__ void run_tile2(const Step2Args& a, int tile, int tile
     }
     combine<P>(g, o.RU[c], B_RD, C_LU, E_LD, o.fU[c], C_fU, B_fD, E_fD, o.gR[c], B_gR, C_gL, E_gL);
   };
-  new_cell2<EQ, P, LIM>(a, gather, mine, (uint32_t)(nj * a.nxn + ni), hx, hy, smax, flags);
+  const uint32_t ncell = (uint32_t)(nj * a.nxn + ni);
+  auto store = [&](int c, double pv, const double (&D)[P + 1][P + 1], unsigned& fl) {
+    store_cell<EQ, P, false>(a, c, ncell, pv, D, fl);
+  };
+  new_cell2<EQ, P, LIM>(a, gather, store, mine, hx, hy, smax, flags);
 }
 
 template <int EQ, int P, bool LIM>
@@ -240,7 +312,8 @@ __device__ __forceinline__ void put_carry(RowCarry<EQ, P>& carry, int c, int lan
 // over one band of rows: no run crosses a strip.  Without BANDS (or with
 // fewer waves than strips) the waves split the strip-major (strip, row)
 // units evenly.  The arithmetic of every unit is the same either way.
-template <int EQ, int P, bool LIM, bool PF, bool BANDS>
+// BUF: buffer addressing of the state (see buffer_form).
+template <int EQ, int P, bool LIM, bool PF, bool BANDS, bool BUF>
 __global__ __launch_bounds__(256) void k2d_half_step_rows(const Step2Args a) {
   constexpr int NC = ncomp<EQ>(), NV = nvert(P), ND = ndof(P);
   __shared__ RowCarry<EQ, P> carry_all[4];
@@ -273,7 +346,8 @@ __global__ __launch_bounds__(256) void k2d_half_step_rows(const Step2Args a) {
   double qn[NC][ND];
   if (PF && u_begin < u_end) {
     const int sx = u_begin / rows, r = u_begin - sx * rows;
-    load_old<EQ, P>(a, map_idx(63 * sx + lane + off, a.nxo, a.periodic_x), map_idx(r + 1 + off, a.nyo, a.periodic_y), qn);
+    load_old<EQ, P, BUF>(a, map_idx(63 * sx + lane + off, a.nxo, a.periodic_x), map_idx(r + 1 + off, a.nyo, a.periodic_y),
+                         qn);
   }
   for (int u = u_begin; u < u_end; ++u) {
     const int sx = u / rows, r = u - sx * rows;
@@ -281,7 +355,7 @@ __global__ __launch_bounds__(256) void k2d_half_step_rows(const Step2Args a) {
     if (u == u_begin || r == 0) {
       // lower parents of new row r: the old row below, expanded afresh
       Old2<EQ, P> o;
-      old_of<EQ, P>(a, i, map_idx(r + off, a.nyo, a.periodic_y), nlx, nly, o);
+      old_of<EQ, P, BUF>(a, i, map_idx(r + off, a.nyo, a.periodic_y), nlx, nly, o);
 #pragma unroll
       for (int c = 0; c < NC; ++c) put_carry<EQ, P>(carry, c, lane, o);
     }
@@ -293,12 +367,12 @@ __global__ __launch_bounds__(256) void k2d_half_step_rows(const Step2Args a) {
         for (int d = 0; d < ND; ++d) q[c][d] = qn[c][d];
       if (u + 1 < u_end) {
         const int sx2 = (u + 1) / rows, r2 = u + 1 - sx2 * rows;
-        load_old<EQ, P>(a, map_idx(63 * sx2 + lane + off, a.nxo, a.periodic_x), map_idx(r2 + 1 + off, a.nyo, a.periodic_y),
-                        qn);
+        load_old<EQ, P, BUF>(a, map_idx(63 * sx2 + lane + off, a.nxo, a.periodic_x),
+                             map_idx(r2 + 1 + off, a.nyo, a.periodic_y), qn);
       }
       __builtin_amdgcn_sched_barrier(0);
     } else {
-      load_old<EQ, P>(a, i, map_idx(r + 1 + off, a.nyo, a.periodic_y), q);
+      load_old<EQ, P, BUF>(a, i, map_idx(r + 1 + off, a.nyo, a.periodic_y), q);
     }
     Old2<EQ, P> o;
     old_cell2<EQ, P>(q, nlx, nly, a.ph, o);
@@ -324,7 +398,11 @@ __global__ __launch_bounds__(256) void k2d_half_step_rows(const Step2Args a) {
       }
       combine<P>(g, A_RU, o.RD[c], C_LU, E_LD, A_fU, C_fU, o.fD[c], E_fD, A_gR, o.gR[c], C_gL, E_gL);
     };
-    new_cell2<EQ, P, LIM>(a, gather, mine, (uint32_t)(r * a.nxn + ni), hx, hy, smax, flags);
+    const uint32_t ncell = (uint32_t)(r * a.nxn + ni);
+    auto store = [&](int c, double pv, const double (&D)[P + 1][P + 1], unsigned& fl) {
+      store_cell<EQ, P, BUF>(a, c, ncell, pv, D, fl);
+    };
+    new_cell2<EQ, P, LIM>(a, gather, store, mine, hx, hy, smax, flags);
   }
   wcc::publish(a.ctrl, a.parts, a.slot, smax, flags);
 }
@@ -361,14 +439,21 @@ __global__ __launch_bounds__(256) void k2d_state_speed(const Step2Args a) {
   wcc::publish(a.ctrl, a.parts, a.slot == 0 ? 2 : a.slot - 1, smax, flags);
 }
 
+// Variants 2 and 3 take the buffer-addressed kernel when a state buffer is
+// below 2 GiB; variant 1 and larger states the pointer form.
 template <int EQ, int P, bool LIM>
 static hipError_t launch_epl(const Step2Args& a, int variant, int blocks, int threads, hipStream_t s) {
-  if (variant == 3)
-    hipLaunchKernelGGL((k2d_half_step_rows<EQ, P, LIM, true, true>), dim3(blocks), dim3(threads), 0, s, a);
+  const bool buf = buffer_form((int64_t)ncomp<EQ>() * ndof(P) * a.plane);
+  if (variant == 3 && buf)
+    hipLaunchKernelGGL((k2d_half_step_rows<EQ, P, LIM, true, true, true>), dim3(blocks), dim3(threads), 0, s, a);
+  else if (variant == 3)
+    hipLaunchKernelGGL((k2d_half_step_rows<EQ, P, LIM, true, true, false>), dim3(blocks), dim3(threads), 0, s, a);
+  else if (variant == 2 && buf)
+    hipLaunchKernelGGL((k2d_half_step_rows<EQ, P, LIM, true, false, true>), dim3(blocks), dim3(threads), 0, s, a);
   else if (variant == 2)
-    hipLaunchKernelGGL((k2d_half_step_rows<EQ, P, LIM, true, false>), dim3(blocks), dim3(threads), 0, s, a);
+    hipLaunchKernelGGL((k2d_half_step_rows<EQ, P, LIM, true, false, false>), dim3(blocks), dim3(threads), 0, s, a);
   else if (variant == 1)
-    hipLaunchKernelGGL((k2d_half_step_rows<EQ, P, LIM, false, false>), dim3(blocks), dim3(threads), 0, s, a);
+    hipLaunchKernelGGL((k2d_half_step_rows<EQ, P, LIM, false, false, false>), dim3(blocks), dim3(threads), 0, s, a);
   else
     hipLaunchKernelGGL((k2d_half_step<EQ, P, LIM>), dim3(blocks), dim3(threads), 0, s, a);
   return hipGetLastError();
@@ -424,41 +509,48 @@ hipError_t launch_state_speed2(const Step2Args& a, int eq, int P, int blocks, hi
 }
 
 template <int EQ, int P, bool LIM>
-static hipError_t occ_epl(int variant, int threads, int* per_cu) {
+static hipError_t occ_epl(int variant, int threads, int64_t plane, int* per_cu) {
+  const bool buf = buffer_form((int64_t)ncomp<EQ>() * ndof(P) * plane);
+  if (variant == 3 && buf)
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k2d_half_step_rows<EQ, P, LIM, true, true, true>,
+                                                        threads, 0);
   if (variant == 3)
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k2d_half_step_rows<EQ, P, LIM, true, true>, threads,
-                                                        0);
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k2d_half_step_rows<EQ, P, LIM, true, true, false>,
+                                                        threads, 0);
+  if (variant == 2 && buf)
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k2d_half_step_rows<EQ, P, LIM, true, false, true>,
+                                                        threads, 0);
   if (variant == 2)
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k2d_half_step_rows<EQ, P, LIM, true, false>, threads,
-                                                        0);
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k2d_half_step_rows<EQ, P, LIM, true, false, false>,
+                                                        threads, 0);
   if (variant == 1)
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k2d_half_step_rows<EQ, P, LIM, false, false>,
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k2d_half_step_rows<EQ, P, LIM, false, false, false>,
                                                         threads, 0);
   return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k2d_half_step<EQ, P, LIM>, threads, 0);
 }
 
 template <int EQ, int P>
-static hipError_t occ_ep(bool lim, int variant, int threads, int* per_cu) {
-  if (lim) return occ_epl<EQ, P, true>(variant, threads, per_cu);
-  return occ_epl<EQ, P, false>(variant, threads, per_cu);
+static hipError_t occ_ep(bool lim, int variant, int threads, int64_t plane, int* per_cu) {
+  if (lim) return occ_epl<EQ, P, true>(variant, threads, plane, per_cu);
+  return occ_epl<EQ, P, false>(variant, threads, plane, per_cu);
 }
 
 template <int EQ>
-static hipError_t occ_e(int P, bool lim, int variant, int threads, int* per_cu) {
+static hipError_t occ_e(int P, bool lim, int variant, int threads, int64_t plane, int* per_cu) {
   switch (P) {
-    case 0: return occ_ep<EQ, 0>(lim, variant, threads, per_cu);
-    case 1: return occ_ep<EQ, 1>(lim, variant, threads, per_cu);
-    case 2: return occ_ep<EQ, 2>(lim, variant, threads, per_cu);
-    case 3: return occ_ep<EQ, 3>(lim, variant, threads, per_cu);
+    case 0: return occ_ep<EQ, 0>(lim, variant, threads, plane, per_cu);
+    case 1: return occ_ep<EQ, 1>(lim, variant, threads, plane, per_cu);
+    case 2: return occ_ep<EQ, 2>(lim, variant, threads, plane, per_cu);
+    case 3: return occ_ep<EQ, 3>(lim, variant, threads, plane, per_cu);
   }
   return hipErrorInvalidValue;
 }
 
-hipError_t occupancy_half_step2(int eq, int P, bool lim, int variant, int threads, int* per_cu) {
+hipError_t occupancy_half_step2(int eq, int P, bool lim, int variant, int threads, int64_t plane, int* per_cu) {
   switch (eq) {
-    case kAdvection: return occ_e<kAdvection>(P, lim, variant, threads, per_cu);
-    case kBurgers: return occ_e<kBurgers>(P, lim, variant, threads, per_cu);
-    case kEuler: return occ_e<kEuler>(P, lim, variant, threads, per_cu);
+    case kAdvection: return occ_e<kAdvection>(P, lim, variant, threads, plane, per_cu);
+    case kBurgers: return occ_e<kBurgers>(P, lim, variant, threads, plane, per_cu);
+    case kEuler: return occ_e<kEuler>(P, lim, variant, threads, plane, per_cu);
   }
   return hipErrorInvalidValue;
 }

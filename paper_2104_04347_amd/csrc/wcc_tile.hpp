@@ -13,8 +13,9 @@
 
 namespace wcc {
 
-// wave_shl:1 -- lane i receives lane i+1 (lane 63 receives `old`).
-__device__ __forceinline__ int dpp_from_next(int x) { return __builtin_amdgcn_update_dpp(0, x, 0x130, 0xF, 0xF, false); }
+// wave_shl:1 -- lane i receives lane i+1; lane 63, which has no source lane,
+// receives 0 (bound_ctrl), so the destination needs no initialising move.
+__device__ __forceinline__ int dpp_from_next(int x) { return __builtin_amdgcn_update_dpp(0, x, 0x130, 0xF, 0xF, true); }
 __device__ __forceinline__ float dpp_from_next(float x) {
   return __int_as_float(dpp_from_next(__float_as_int(x)));
 }
