@@ -279,3 +279,25 @@ def test_autotune_2d_keys_and_choice(tmp_path, monkeypatch):
     assert (best["variant"], best["threads"], best["blocks"]) == (2, 256, 256) and s.shape == (2, 256, 256)
     assert autotune.key_2d(s) == "2d/burgers/P3/lim/2048x2048/periodic,periodic"
     assert autotune.cached_2d(s)["blocks"] == 256
+
+
+def test_autotune_refine_picks_the_steady_state_best():
+    """A candidate that looked fastest in its single sweep timing (a clock
+    transition) loses the round-robin re-timing to the one that is faster in
+    steady state; finalists are re-timed in rotated order."""
+    cands = [{"name": "A", "ms_per_step": 0.80}, {"name": "B", "ms_per_step": 0.90},
+             {"name": "C", "ms_per_step": 0.95}, {"name": "D", "ms_per_step": 0.99},
+             {"name": "E", "ms_per_step": 2.0}]
+    steady = {"A": 1.0, "B": 0.9, "C": 0.97, "D": 1.1, "E": 0.5}
+    order = []
+
+    def time_one(c):
+        order.append(c["name"])
+        # the first timing of each round is disturbed (+20%)
+        return steady[c["name"]] * (1.2 if len(order) % 4 == 1 else 1.0)
+
+    best = autotune.refine(cands, time_one, top=4, rounds=3)
+    assert best["name"] == "B" and best["refined_ms"] == 0.9
+    assert "E" not in order                      # only the four fastest of the sweep are finalists
+    assert order[:4] == ["A", "B", "C", "D"] and order[4:8] == ["B", "C", "D", "A"]
+    assert all(len(c["refined_all"]) == 3 for c in cands[:4])
