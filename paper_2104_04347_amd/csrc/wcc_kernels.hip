@@ -28,6 +28,19 @@
 
 namespace wcc {
 
+// Register budget: the least number of waves per SIMD a kernel is compiled
+// for (1: no bound, the compiler's own allocation).  The binary64 Euler
+// kernels of degree 3 with direct stores allocate 130 VGPRs when left free,
+// two over the 128 that four waves per SIMD allow; held to four waves they fit
+// without spilling and ran ~2.5% faster on the N = 2^20 workload.  Held to four
+// waves, the prefetching variants of the same kernel spill and run 30-40%
+// slower, the binary32 kernels already run at four to six, and the other
+// binary64 kernels sit well below or well above a step of the register file.
+template <int EQ, int P, class R, int PF>
+constexpr int min_waves_per_simd() {
+  return (EQ == kEuler && P == 3 && sizeof(R) == 8 && PF == 0) ? 4 : 1;
+}
+
 // Variant bits.  PF & 1: each wave loads the inputs of its next tile before
 // expanding the current one, so every wave keeps one tile of loads in flight
 // while it computes (costs the registers of one tile's inputs).  PF & 2: the
@@ -35,7 +48,8 @@ namespace wcc {
 // barriers per iteration of the block's waves; pays where the state does not
 // fit the caches).
 template <int EQ, int P, bool LIM, class R, int PF>
-__global__ __launch_bounds__(256) void k_half_step(const StepArgs<R> a) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(min_waves_per_simd<EQ, P, R, PF>())))
+void k_half_step(const StepArgs<R> a) {
   double dt;
   if (!step_time(a.ctrl, a.parts, a.slot, a.dx, a.dt_fixed, blockIdx.x == 0 && threadIdx.x < 64, dt)) return;
   const double lam = dt / a.dx;
