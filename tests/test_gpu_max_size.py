@@ -86,7 +86,7 @@ def test_2d_max_cells_transmissive_burgers():
 # planes' offsets near the top of the 32-bit range); 2600^2 -> 2.163e9 B, the
 # pointer form.
 @pytest.mark.timeout(900)
-@pytest.mark.parametrize("N,variant", [(2560, 3), (2560, 2), (2600, 3)])
+@pytest.mark.parametrize("N,variant", [(2560, 3), (2560, 2), (2600, 3), (2600, 2)])
 def test_2d_euler_at_the_buffer_offset_limit(N, variant):
     P = 3
     h = 2.0 ** -9
