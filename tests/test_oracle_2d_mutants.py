@@ -10,6 +10,7 @@ import oracle
 from oracle import build as obuild
 
 import test_oracle_2d as t2
+import test_oracle_2d_limiter as t2l
 import test_oracle_2d_transmissive as t2t
 
 MUTANTS = {
@@ -41,11 +42,21 @@ MUTANTS = {
     "left eigenvector sign": ("{-ut, -ny, nx, 0.0}", "{ut, -ny, nx, 0.0}"),
     "right eigenvector energy entry": ("{1.0, u, vv, 0.5 * q2}", "{1.0, u, vv, q2}"),
     "tangential velocity sign": ("ut = std::fma(vv, nx, -(u * ny))", "ut = std::fma(vv, nx, u * ny)"),
+    "candidate weights unsquared": ("      wh[m] = rm * rm;", "      wh[m] = rm;"),
+    "back-projection with the left eigenvectors": ("out[r][k][l] = (f == 0) ? R[f][r] * cD[k][l] : std::fma(R[f][r], cD[k][l], out[r][k][l]);",
+                                                   "out[r][k][l] = (f == 0) ? L[f][r] * cD[k][l] : std::fma(L[f][r], cD[k][l], out[r][k][l]);"),
+    "vertex values projected from one vertex": ("for (int r = 0; r < 4; ++r) x[r] = v[r][vtx];",
+                                                "for (int r = 0; r < 4; ++r) x[r] = v[r][0];"),
     "transmissive ghost wraps in x": ("    return i < 0 ? 0 : (i >= nx ? nx - 1 : i);", "    return (i % nx + nx) % nx;"),
     "transmissive edge mesh missing": ("ex = (px || parity == 1) ? 0 : 1", "ex = (px || parity == 0) ? 0 : 1"),
     "y edges follow x": ("const bool px = pb.bc == 0, py = bc_y_of(pb) == 0;",
                          "const bool px = pb.bc == 0, py = px;"),
 }
+
+
+def _brute_ok(eq):
+    worst, acted = t2l.limiter_deviation(eq, 2, N=12)
+    assert worst <= t2l.TOL[2] and acted >= 10
 
 
 def quick_pins() -> list:
@@ -68,6 +79,7 @@ def quick_pins() -> list:
         ("transmissive 1D Euler", lambda: t2t.test_reduces_to_1d_euler_transmissive(2)),
         ("transmissive interior", lambda: t2t.test_interior_equals_periodic("burgers", 3)),
         ("mixed edges 1D", lambda: t2t.test_periodic_x_transmissive_y_reduces_to_1d(2)),
+        ("limiter brute force", lambda: [_brute_ok(eq) for eq in ("burgers", "euler")]),
     ]
     failed = []
     for name, fn in checks:
