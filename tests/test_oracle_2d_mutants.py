@@ -10,6 +10,7 @@ import oracle
 from oracle import build as obuild
 
 import test_oracle_2d as t2
+import test_oracle_2d_ck as t2ck
 import test_oracle_2d_limiter as t2l
 import test_oracle_2d_transmissive as t2t
 
@@ -42,6 +43,10 @@ MUTANTS = {
     "left eigenvector sign": ("{-ut, -ny, nx, 0.0}", "{ut, -ny, nx, 0.0}"),
     "right eigenvector energy entry": ("{1.0, u, vv, 0.5 * q2}", "{1.0, u, vv, q2}"),
     "tangential velocity sign": ("ut = std::fma(vv, nx, -(u * ny))", "ut = std::fma(vv, nx, u * ny)"),
+    "Taylor product time index": ("s = std::fma(X[a][b][c], Y[k - a][l - b][m - c], s);",
+                                  "s = std::fma(X[a][b][c], Y[k - a][l - b][m], s);"),
+    "Taylor quotient y index": ("s = std::fma(-Rho[a][b][c], V[k - a][l - b][m - c], s);",
+                                "s = std::fma(-Rho[a][b][c], V[k - a][l][m - c], s);"),
     "candidate weights unsquared": ("      wh[m] = rm * rm;", "      wh[m] = rm;"),
     "back-projection with the left eigenvectors": ("out[r][k][l] = (f == 0) ? R[f][r] * cD[k][l] : std::fma(R[f][r], cD[k][l], out[r][k][l]);",
                                                    "out[r][k][l] = (f == 0) ? L[f][r] * cD[k][l] : std::fma(L[f][r], cD[k][l], out[r][k][l]);"),
@@ -80,6 +85,8 @@ def quick_pins() -> list:
         ("transmissive interior", lambda: t2t.test_interior_equals_periodic("burgers", 3)),
         ("mixed edges 1D", lambda: t2t.test_periodic_x_transmissive_y_reduces_to_1d(2)),
         ("limiter brute force", lambda: [_brute_ok(eq) for eq in ("burgers", "euler")]),
+        ("CK exact", lambda: [t2ck.test_ck_expansion_matches_exact_rational_solution(e, p)
+                              for e, p in (("euler", 2), ("euler", 3))]),
     ]
     failed = []
     for name, fn in checks:
