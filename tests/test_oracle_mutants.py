@@ -21,6 +21,7 @@ from paper_2104_04347_amd import inputs
 
 from test_oracle_linear import _mat, oracle_matrices
 import test_oracle_boundary_speed as tbs
+import test_oracle_ck_exact as tce
 import test_oracle_euler_limiter as tel
 
 import json
@@ -173,7 +174,12 @@ def quick_pins(first_only: bool = False) -> list:
         worst, acted = tel.euler_limiter_deviation(2, 96, steps=6)
         return worst <= tel.TOL[2] and acted >= 5
 
+    def ck_exact():
+        tce.test_ck_triangle_matches_exact_rational_solution("euler", 3)
+        return True
+
     check("appendix A", appendix)
+    check("CK exact", ck_exact)
     check("Euler characteristic limiter", euler_limiter)
     check("Dirichlet ghosts", dirichlet_ends)
     check("wave speed", tbs.wave_speed_time_steps_ok)
