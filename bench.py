@@ -77,16 +77,40 @@ def valu_insts(kernel: str, N: int, sources: str = "1d"):
     return e["sq_insts_valu"]
 
 
+def shader_clock(kernel: str, N: int, sources: str = "1d"):
+    """Shader clock (MHz) the kernel's waves ran at under the benchmark's
+    sustained load, from the committed timeline record, or None when it is
+    for another build or size."""
+    path = os.path.join(ROOT, "profiles", "clock.json")
+    try:
+        with open(path) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    from paper_2104_04347_amd.profsum import kernel_source_hash
+    e = rec.get(kernel)
+    if not e or e.get("source_sha256") != kernel_source_hash(sources) or e.get("N") != N:
+        return None
+    return e["clock_mhz"]
+
+
 def issue_roof(kernel: str, N: int, launch_s: float, sources: str = "1d"):
     """VALU issue roof: the launch's VALU instructions at one per 4 cycles on
-    every SIMD at the peak clock, against the measured launch time."""
+    every SIMD at the peak clock, against the measured launch time; with a
+    committed clock record, also at the clock the waves ran at."""
     insts = valu_insts(kernel, N, sources)
     if insts is None:
         return None
     t_issue = insts / VALU_ISSUE_PEAK
-    return {"bound": "alu", "unit": "Ginst/s", "achieved": round(insts / launch_s / 1e9, 1),
-            "peak": round(VALU_ISSUE_PEAK / 1e9, 1), "frac": round(t_issue / launch_s, 4),
-            "valu_insts_per_launch": insts, "issue_floor_us": round(t_issue * 1e6, 2)}
+    out = {"bound": "alu", "unit": "Ginst/s", "achieved": round(insts / launch_s / 1e9, 1),
+           "peak": round(VALU_ISSUE_PEAK / 1e9, 1), "frac": round(t_issue / launch_s, 4),
+           "valu_insts_per_launch": insts, "issue_floor_us": round(t_issue * 1e6, 2)}
+    mhz = shader_clock(kernel, N, sources)
+    if mhz:
+        at = VALU_ISSUE_PEAK * (mhz * 1e6 / CLOCK_HZ)
+        out |= {"shader_clock_mhz": mhz, "peak_at_clock": round(at / 1e9, 1),
+                "frac_at_clock": round(insts / at / launch_s, 4)}
+    return out
 
 
 def flop_counts():
@@ -137,10 +161,8 @@ def launch_shape_single(args, s, q0, cfl=None, **tune_kw) -> dict:
 
 def kernel_record(precision: str, P: int, variant: int):
     """Key and source set of the counter records of the 1D Euler kernel."""
-    bulk = "f64" if precision == "fp64" else "f32"
-    if variant == 4:
-        return f"k_half_step_wide<euler,P={P},limiter,{bulk}>", "1d_wide"
-    return f"k_half_step<euler,P={P},limiter,{bulk},variant={variant}>", "1d"
+    from paper_2104_04347_amd import records
+    return records.key_1d(precision, P, variant)
 
 
 def time_single(args, precision: str, q0, keep_state: bool = False):
@@ -318,13 +340,12 @@ def time_2d(args):
         cells = N * N if bc == "periodic" else 0.5 * ((N + 1) ** 2 + N * N)
         dofs = cells * nc * nd * args.steps2d
         bpl = 2.0 * cells * nc * nd * 8
-        form = {1: "no prefetch", 2: "prefetch", 3: "prefetch,bands"}.get(launch["variant"], "8x8 tiles")
-        kernel = f"k2d_half_step_rows<{eq},P={P},{'limiter' if lim else 'no limiter'},{form}>"
+        from paper_2104_04347_amd import records
+        kernel = records.kernel_2d(eq, P, lim, launch["variant"])
         # the counter record belongs to the kernel, the mesh and the launch
         # grid (the grid sets how many priming rows are re-read)
         eff = s.get_launch()                   # the grid actually launched (0 resolved)
-        rec_key = (kernel + ("" if bc == "periodic" else ",transmissive") +
-                   f",grid={eff['threads']}x{eff['blocks']}")
+        rec_key = records.key_2d(eq, P, lim, launch["variant"], bc == "periodic", eff["threads"], eff["blocks"])
         e = {"value": dofs / wall, "unit": "cell-DOF updates/s", "N": N, "P": P, "limiter": lim, "bc": bc,
              "cfl": cfl, "half_steps": args.steps2d, "kernel": kernel, "launch": launch, "launch_us": launch_s * 1e6,
              "bytes_per_launch": bpl, "hbm_frac": bpl / launch_s / HBM_PEAK,

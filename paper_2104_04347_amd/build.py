@@ -4,6 +4,11 @@ Every translation unit is compiled by hipcc for gfx950 only, with
 -ffp-contract=off (the binary64 path follows a fixed operation order) and
 without packed-FP32 instructions; the objects are compiled in parallel and
 linked into one shared library that exports the C ABI of include/wcc.h.
+
+The same build links the diagnostic library libwcc_timeline.so: the product
+objects with the three kernel translation units replaced by their timestamped
+builds (csrc/wcc_timeline_*.hip, which include the kernel sources unchanged).
+Only paper_2104_04347_amd/timeline.py loads it.
 """
 from __future__ import annotations
 
@@ -17,9 +22,13 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT_DIR = os.path.join(HERE, "_lib")
 LIB = os.path.join(OUT_DIR, "libwcc.so")
+TIMELINE_LIB = os.path.join(OUT_DIR, "libwcc_timeline.so")
 ROOT = os.path.dirname(HERE)
 
 SOURCES = ["wcc_kernels.hip", "wcc_kernels_wide.hip", "wcc_ctrl.hip", "wcc_batch.hip", "wcc_api.hip", "wcc2d_kernels.hip", "wcc2d_api.hip"]
+# diagnostic build: kernel translation unit -> its timestamped replacement
+TIMELINE_SOURCES = {"wcc_kernels.hip": "wcc_timeline_1d.hip", "wcc_kernels_wide.hip": "wcc_timeline_1d_wide.hip",
+                    "wcc2d_kernels.hip": "wcc_timeline_2d.hip"}
 ARCH = "gfx950"
 
 HIPFLAGS = [
@@ -65,20 +74,28 @@ def _compile(src: str, obj: str, verbose: bool) -> None:
         print(out)
 
 
-def build(verbose: bool = False) -> str:
-    os.makedirs(OUT_DIR, exist_ok=True)
-    objs = [os.path.join(OUT_DIR, s.replace(".hip", ".o")) for s in SOURCES]
-    with cf.ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
-        list(ex.map(lambda so: _compile(so[0], so[1], verbose), zip(SOURCES, objs)))
-    tmp = LIB + ".tmp"
+def _link(out: str, objs: list, verbose: bool) -> None:
+    tmp = out + ".tmp"
     tl = torch_lib_dir()
     cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-no-hip-rt", "-o", tmp, *objs,
            f"-L{tl}", "-l:libamdhip64.so", f"-Wl,-rpath,{tl}"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
-    os.replace(tmp, LIB)
-    for o in objs:
+    os.replace(tmp, out)
+
+
+def build(verbose: bool = False) -> str:
+    os.makedirs(OUT_DIR, exist_ok=True)
+    srcs = SOURCES + list(TIMELINE_SOURCES.values())
+    obj = {s: os.path.join(OUT_DIR, s.replace(".hip", ".o")) for s in srcs}
+    # the two longest compiles (the 2D kernels and their timestamped build) first
+    order = sorted(srcs, key=lambda s: s not in ("wcc2d_kernels.hip", "wcc_timeline_2d.hip"))
+    with cf.ThreadPoolExecutor(max_workers=min(len(srcs), os.cpu_count() or 1)) as ex:
+        list(ex.map(lambda s: _compile(s, obj[s], verbose), order))
+    _link(LIB, [obj[s] for s in SOURCES], verbose)
+    _link(TIMELINE_LIB, [obj[TIMELINE_SOURCES.get(s, s)] for s in SOURCES], verbose)
+    for o in obj.values():
         os.remove(o)
     return LIB
 

@@ -1,0 +1,11 @@
+// wcc_timeline_1d_wide.hip -- diagnostic build of the 1D half-step kernels on 128-cell tiles with per-wave timestamps
+// (linked into libwcc_timeline.so in place of wcc_kernels_wide.hip; see wcc_timeline.hpp).
+#include "wcc_timeline.hpp"
+
+#define step_time(...) step_time_tl(__VA_ARGS__)
+#define publish(...) publish_tl(__VA_ARGS__)
+#include "wcc_kernels_wide.hip"
+#undef step_time
+#undef publish
+
+WCC_TIMELINE_ENTRY_POINTS(1d_wide)

@@ -8,7 +8,7 @@ import numpy as np
 import pytest
 
 import bench
-from paper_2104_04347_amd import autotune, profsum
+from paper_2104_04347_amd import autotune, profsum, records, timeline
 
 
 def test_cells_updated():
@@ -115,6 +115,34 @@ def test_valu_instruction_record_and_issue_roof(tmp_path, monkeypatch):
     assert abs(r["frac"] - round(floor / launch_s, 4)) < 1e-12
     assert abs(r["issue_floor_us"] - round(floor * 1e6, 2)) < 1e-12
     assert bench.issue_roof("key1", 129, launch_s) is None
+    assert "frac_at_clock" not in r
+    # with a clock record for the same build and size: the roof at that clock
+    timeline.record("key1", "1d", 128, {"clock_mhz": 1800.0, "clock_mhz_p0_10_50_90_100": [1700.0] * 5,
+                                        "launch_us": 10.0, "mean_waves_per_simd": 3.0},
+                    path=str(tmp_path / "profiles" / "clock.json"))
+    r = bench.issue_roof("key1", 128, launch_s)
+    assert r["shader_clock_mhz"] == 1800.0
+    assert abs(r["frac_at_clock"] - round(floor * 2400.0 / 1800.0 / launch_s, 4)) < 1e-12
+    assert bench.shader_clock("key1", 128, "2d") is None and bench.shader_clock("key1", 64) is None
+
+
+def test_committed_clock_records_match_the_sources():
+    path = os.path.join(bench.ROOT, "profiles", "clock.json")
+    if not os.path.exists(path):
+        pytest.skip("no clock records committed")
+    for key, e in json.load(open(path)).items():
+        src = "2d" if key.startswith("k2d") else ("1d_wide" if key.startswith("k_half_step_wide") else "1d")
+        assert e["source_sha256"] == profsum.kernel_source_hash(src), key
+        assert 300.0 < bench.shader_clock(key, e["N"], src) < 3000.0
+
+
+def test_record_keys_are_those_of_the_committed_counter_records():
+    keys = set(json.load(open(os.path.join(bench.ROOT, "profiles", "valu_insts.json"))))
+    assert records.key_1d("fp64", 3, 0) == ("k_half_step<euler,P=3,limiter,f64,variant=0>", "1d")
+    assert records.key_1d("fp32_mixed", 3, 4) == ("k_half_step_wide<euler,P=3,limiter,f32>", "1d_wide")
+    assert records.key_2d("euler", 3, True, 3, False, 256, 256) in keys
+    assert records.key_2d("euler", 3, False, 3, True, 256, 256) in keys
+    assert records.key_2d("burgers", 3, True, 3, True, 256, 512) in keys
 
 
 def test_autotune_keys():
