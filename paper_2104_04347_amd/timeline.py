@@ -17,9 +17,12 @@ place of the product one):
 The workload of each case is the benchmark leg of the same name (sizes,
 initial data, CFL number); the launch shape is the autotuner's cached one when
 the cache holds it, else the library default, unless --variant/--threads/
---blocks are given.  `--warmup` half-steps run first; the records are then
-cleared and `--steps` more half-steps run back to back (the clock settles
-under the sustained load within them); the records hold the last of them.
+--blocks are given.  The records are cleared before the state is written;
+then `--warmup` and `--steps` half-steps run back to back with no host
+synchronisation between them, so the clock has settled under the sustained
+load; the records hold the last launch and the launch time is the mean over
+the last `--steps`.  (The state write stamps only the exit of its wave-speed
+kernel's waves; records without an entry stamp are ignored.)
 `--record` stores the clock in profiles/clock.json under the kernel's record
 key (the key of its counter records), stamped with the SHA-256 of the kernel
 sources (the diagnostic build compiles the same sources), for the
@@ -122,10 +125,9 @@ def run_1d(lib, args) -> tuple:
     s = binding.Solver("euler", P, N, "transmissive", limiter=True, precision=args.precision)
     shape = _shape_1d(s, args)
     fam = "1d_wide" if shape["variant"] == 4 else "1d"
+    clear(lib, fam)
     s.write(q0)
     s.run(args.warmup, CFL_1D)
-    _sync()
-    clear(lib, fam)
     s.run(args.steps, CFL_1D)
     _sync()
     launch_us = s.last_run_ms() * 1e3 / args.steps
@@ -159,10 +161,9 @@ def run_2d(lib, args) -> tuple:
     else:
         s.set_launch(args.threads, args.blocks, args.variant)
     shape = s.get_launch()
+    clear(lib, "2d")
     s.write(q0)
     s.run(args.warmup, cfl)
-    _sync()
-    clear(lib, "2d")
     s.run(args.steps, cfl)
     _sync()
     launch_us = s.last_run_ms() * 1e3 / args.steps
@@ -207,7 +208,8 @@ def main(argv=None) -> None:
     ap.add_argument("--record", action="store_true", help="store the clock in profiles/clock.json")
     args = ap.parse_args(argv)
     one_d = args.case == "1d"
-    args.warmup = args.warmup or (400 if one_d else 40)
+    # about 0.2 s of back-to-back half-steps before the recorded ones
+    args.warmup = args.warmup or (5000 if one_d else 1000)
     args.steps = args.steps or (200 if one_d else 20)
     lib = load()
     head, rec, launch_us = (run_1d if one_d else run_2d)(lib, args)
