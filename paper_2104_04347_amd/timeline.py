@@ -100,7 +100,11 @@ def summarize(rec: np.ndarray, launch_us: float) -> dict:
     hw = r["hw_id"].astype(np.int64)
     simd = (r["xcc_id"].astype(np.int64) & 15) << 16 | (hw >> 4 & 3) | (hw >> 8 & 15) << 2 | (hw >> 12 & 0xF) << 6
     nsimd = len(np.unique(simd))
+    # clocks from waves that lived at least 1 us (100 ticks of the constant
+    # clock), unless none did
     long_ = life_us >= 1.0
+    if not long_.any():
+        long_ = np.ones_like(long_)
     mhz = c / ((t1 - t0) / RT_HZ) / 1e6
     xcc = r["xcc_id"].astype(np.int64) & 15
     pct = lambda a, q: [round(float(x), 2) for x in np.percentile(a, q)]   # noqa: E731

@@ -66,6 +66,16 @@ def test_summary_of_synthetic_records():
     assert s["clock_mhz_by_xcd"] == {3: s["clock_mhz"]}
 
 
+def test_summary_of_short_lived_waves():
+    rec = np.zeros(timeline.WAVES, dtype=timeline.REC)
+    rec[:2]["t0"] = 1000
+    rec[:2]["t1"] = 1050                      # 0.5 us
+    rec[:2]["c0"] = 0
+    rec[:2]["c1"] = 1000                      # 2 GHz
+    s = timeline.summarize(rec, launch_us=1.0)
+    assert s["waves"] == 2 and s["clock_mhz"] == 2000.0
+
+
 def test_summary_refuses_empty_records():
     with pytest.raises(RuntimeError):
         timeline.summarize(np.zeros(timeline.WAVES, dtype=timeline.REC), 1.0)
