@@ -94,3 +94,43 @@ def test_recorded_run(case):
     assert s["waves"] > 256 and s["simds"] > 256
     assert 0 < s["wave_life_us_p0_10_50_90_100"][-1] <= s["span_us"]
     assert 300.0 < s["clock_mhz"] < 3000.0
+
+
+_SAME_BITS = r"""
+import hashlib, sys
+import numpy as np
+import torch
+from paper_2104_04347_amd import binding, inputs
+binding.load(sys.argv[1])
+h = hashlib.sha256()
+q0, _ = inputs.euler_riemann(0, 3, 300)
+s = binding.Solver("euler", 3, 300, "transmissive", limiter=True, precision="fp64")
+s.write(q0)
+s.run(50, 0.25)
+q, info = s.read()
+h.update(q.tobytes()); h.update(np.float64(info.t).tobytes())
+s.close()
+q0 = inputs.riemann2d(1, 2, 24)
+s = binding.Solver2D("euler", 2, 24, 24, limiter=True, bc="transmissive", x_left=-1.0, x_right=1.0, y_left=-1.0,
+                     y_right=1.0)
+s.write(q0)
+s.run(6, 0.3)
+q, info = s.read()
+h.update(q.tobytes()); h.update(np.float64(info.t).tobytes())
+s.close()
+print(h.hexdigest())
+"""
+
+
+@pytest.mark.gpu
+def test_diagnostic_build_computes_the_same_bits():
+    """The timestamped kernels are the product kernels: 1D and 2D runs give
+    the same bits with either library (each in a process of its own)."""
+    out = []
+    for lib in (build.LIB, build.TIMELINE_LIB):
+        print("same-bits run with", lib, flush=True)
+        r = subprocess.run([sys.executable, "-c", _SAME_BITS, lib], cwd=ROOT, capture_output=True, text=True,
+                           timeout=300)
+        assert r.returncode == 0, r.stderr[-3000:]
+        out.append(r.stdout.strip().splitlines()[-1])
+    assert out[0] == out[1]
