@@ -78,9 +78,10 @@ def valu_insts(kernel: str, N: int, sources: str = "1d"):
 
 
 def shader_clock(kernel: str, N: int, sources: str = "1d"):
-    """Shader clock (MHz) the kernel's waves ran at under the benchmark's
-    sustained load, from the committed timeline record, or None when it is
-    for another build or size."""
+    """Shader clock (MHz) that the per-wave timeline measured for this kernel
+    on the benchmark's workload (the committed record: 0.2 s of back-to-back
+    half-steps, possibly on another box), or None when the record is for
+    another build or size."""
     path = os.path.join(ROOT, "profiles", "clock.json")
     try:
         with open(path) as f:
