@@ -14,6 +14,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "wcc_rn.hpp"
+
 namespace wcc2d {
 
 enum { kAdvection = 0, kBurgers = 1, kEuler = 2 };
@@ -149,7 +151,7 @@ __device__ __forceinline__ void old_cell2(const double (&q)[ncomp<EQ>()][ndof(P)
           Fl[0][d] = h;
           Gl[0][d] = h;
         } else {
-          if (k == 0 && l == 0 && m == 0) rinv = 1.0 / T[0].v[0][0][0];
+          if (k == 0 && l == 0 && m == 0) rinv = wcc::div_rn(1.0, T[0].v[0][0][0]);
           u.v[k][l][m] = tquot3<P>(T[1], T[0], u, rinv, k, l, m);
           v.v[k][l][m] = tquot3<P>(T[2], T[0], v, rinv, k, l, m);
           const double kx = tprod3<P>(T[1], u, k, l, m);
@@ -284,8 +286,8 @@ __device__ __forceinline__ void limit2d(double eps, double abar, double (&D)[P +
   const double b3 = __builtin_fma(uy3, uy3, ux3 * ux3), b4 = __builtin_fma(uy4, uy4, ux4 * ux4);
   double wh0, wh1, wh2, wh3, wh4;
   if constexpr (P == 1) {
-    const double q0 = 1.0 / (b0 + eps), q1 = 1.0 / (b1 + eps), q2 = 1.0 / (b2 + eps), q3 = 1.0 / (b3 + eps),
-                 q4 = 1.0 / (b4 + eps);
+    const double q0 = wcc::div_rn(1.0, b0 + eps), q1 = wcc::div_rn(1.0, b1 + eps), q2 = wcc::div_rn(1.0, b2 + eps),
+                 q3 = wcc::div_rn(1.0, b3 + eps), q4 = wcc::div_rn(1.0, b4 + eps);
     wh0 = q0 * q0; wh1 = q1 * q1; wh2 = q2 * q2; wh3 = q3 * q3; wh4 = q4 * q4;
   } else {
     double p0 = abar;
@@ -317,12 +319,12 @@ __device__ __forceinline__ void limit2d(double eps, double abar, double (&D)[P +
 #pragma unroll
     for (int k = 1; k <= P; ++k) tau = __builtin_fma(D[k][P - k], D[k][P - k], tau);
     const double st = sigma * tau;
-    const double r0 = st / __builtin_fma(b0, b0, eps), r1 = st / __builtin_fma(b1, b1, eps),
-                 r2 = st / __builtin_fma(b2, b2, eps), r3 = st / __builtin_fma(b3, b3, eps),
-                 r4 = st / __builtin_fma(b4, b4, eps);
+    const double r0 = wcc::div_rn(st, __builtin_fma(b0, b0, eps)), r1 = wcc::div_rn(st, __builtin_fma(b1, b1, eps)),
+                 r2 = wcc::div_rn(st, __builtin_fma(b2, b2, eps)), r3 = wcc::div_rn(st, __builtin_fma(b3, b3, eps)),
+                 r4 = wcc::div_rn(st, __builtin_fma(b4, b4, eps));
     wh0 = __builtin_fma(r0, r0, 1.0); wh1 = r1 * r1; wh2 = r2 * r2; wh3 = r3 * r3; wh4 = r4 * r4;
   }
-  const double inv = 1.0 / ((((wh0 + wh1) + wh2) + wh3) + wh4);
+  const double inv = wcc::div_rn(1.0, (((wh0 + wh1) + wh2) + wh3) + wh4);
   const double w0 = wh0 * inv, w1 = wh1 * inv, w2_ = wh2 * inv, w3 = wh3 * inv, w4 = wh4 * inv;
   double dx1 = w0 * D[1][0], dy1 = w0 * D[0][1];
   dx1 = __builtin_fma(w1, ux1, dx1); dy1 = __builtin_fma(w1, uy1, dy1);
@@ -346,21 +348,21 @@ __device__ __forceinline__ void limit2d(double eps, double abar, double (&D)[P +
 template <int P>
 __device__ __forceinline__ void char_limit2d(const Phys2& ph, double dx, double dy, const double (&ab)[4],
                                              double (&D)[4][P + 1][P + 1], const double (&v)[4][4]) {
-  const double gx = D[3][1][0] / dx, gy = D[3][0][1] / dy;
+  const double gx = wcc::div_rn(D[3][1][0], dx), gy = wcc::div_rn(D[3][0][1], dy);
   const double g2 = __builtin_fma(gy, gy, gx * gx);
   double nx = 1.0, ny = 0.0;
   if (g2 > 0.0) {
-    const double gn = __builtin_sqrt(g2);
-    nx = gx / gn;
-    ny = gy / gn;
+    const double gn = wcc::sqrt_rn(g2);
+    nx = wcc::div_rn(gx, gn);
+    ny = wcc::div_rn(gy, gn);
   }
-  const double rho = ab[0], u = ab[1] / rho, vv = ab[2] / rho;
+  const double rho = ab[0], u = wcc::div_rn(ab[1], rho), vv = wcc::div_rn(ab[2], rho);
   const double p = ph.gm1 * (ab[3] - 0.5 * __builtin_fma(ab[2], vv, ab[1] * u));
-  const double c = __builtin_sqrt((ph.gamma * p) / rho);
-  const double H = (ab[3] + p) / rho;
+  const double c = wcc::sqrt_rn(wcc::div_rn(ph.gamma * p, rho));
+  const double H = wcc::div_rn(ab[3] + p, rho);
   const double un = __builtin_fma(vv, ny, u * nx), ut = __builtin_fma(vv, nx, -(u * ny));
   const double q2 = __builtin_fma(vv, vv, u * u);
-  const double ic = 1.0 / c;
+  const double ic = wcc::div_rn(1.0, c);
   const double b1 = ph.gm1 * (ic * ic), b2 = 0.5 * (q2 * b1);
   const double uic = un * ic, nxic = nx * ic, nyic = ny * ic, b1u = b1 * u, b1v = b1 * vv;
   const double L[4][4] = {{0.5 * (b2 + uic), -0.5 * (b1u + nxic), -0.5 * (b1v + nyic), 0.5 * b1},
@@ -477,9 +479,9 @@ __device__ __forceinline__ double speed_rate(const double (&ab)[ncomp<EQ>()], co
     return __builtin_fma(s, idy, s * idx);
   } else {
     const double rho = ab[0];
-    const double u = ab[1] / rho, v = ab[2] / rho;
+    const double u = wcc::div_rn(ab[1], rho), v = wcc::div_rn(ab[2], rho);
     const double p = ph.gm1 * (ab[3] - 0.5 * __builtin_fma(ab[2], v, ab[1] * u));
-    const double c = __builtin_sqrt((ph.gamma * p) / rho);
+    const double c = wcc::sqrt_rn(wcc::div_rn(ph.gamma * p, rho));
     if (!(rho > 0.0) || !(p > 0.0)) flag |= 2u;
     return __builtin_fma(__builtin_fabs(v) + c, idy, (__builtin_fabs(u) + c) * idx);
   }

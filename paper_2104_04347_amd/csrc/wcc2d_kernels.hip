@@ -264,7 +264,7 @@ __global__ __launch_bounds__(256) void k2d_half_step(const Step2Args a) {
   double dt;
   // dx = 1: the ring forms dt = (cfl * 1) / smax, smax being a rate (1/time)
   if (!wcc::step_time(a.ctrl, a.parts, a.slot, 1.0, a.dt_fixed, blockIdx.x == 0 && threadIdx.x < 64, dt)) return;
-  const double lamx = dt / a.dx, lamy = dt / a.dy;
+  const double lamx = wcc::div_rn(dt, a.dx), lamy = wcc::div_rn(dt, a.dy);
   const double nlx = -lamx, nly = -lamy, hx = 0.5 * lamx, hy = 0.5 * lamy;
   double smax = 0.0;
   unsigned flags = 0u;
@@ -338,7 +338,7 @@ __global__ __launch_bounds__(256) void k2d_half_step_rows(const Step2Args a) {
   }
   double dt;
   if (!wcc::step_time(a.ctrl, a.parts, a.slot, 1.0, a.dt_fixed, blockIdx.x == 0 && threadIdx.x < 64, dt)) return;
-  const double lamx = dt / a.dx, lamy = dt / a.dy;
+  const double lamx = wcc::div_rn(dt, a.dx), lamy = wcc::div_rn(dt, a.dy);
   const double nlx = -lamx, nly = -lamy, hx = 0.5 * lamx, hy = 0.5 * lamy;
   const int off = a.parity_old == 0 ? 0 : -1;
   double smax = 0.0;

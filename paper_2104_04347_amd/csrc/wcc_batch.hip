@@ -83,7 +83,7 @@ __device__ __forceinline__ void batch_tile(const BatchArgs<R>& a, const BatchIns
   const bool go = step_time(ctrl, nullptr, a.slot, in.dx, 0.0, first == 0, dt);
   if (!go) return;
   const StepArgs<R> s = instance_args(a, in, bc, ctrl);
-  const double lam = dt / in.dx;
+  const double lam = div_rn(dt, in.dx);
   if ((int64_t)first * 63 < s.n_new) run_tile<EQ, P, LIM, R>(s, first, lam, (R)(-lam), lane, smax, flags);
 }
 
@@ -99,7 +99,7 @@ __device__ __forceinline__ void batch_tile_staged(const BatchArgs<R>& a, const B
   const bool go = step_time(ctrl, nullptr, a.slot, in.dx, 0.0, first == 0, dt);
   if (!go) return;
   const StepArgs<R> s = instance_args(a, in, bc, ctrl);
-  const double lam = dt / in.dx;
+  const double lam = div_rn(dt, in.dx);
   if ((int64_t)first * 63 >= s.n_new) return;
   TileIn<EQ, P, R> ti;
   fetch_tile<EQ, P, R>(s, first, lane, ti);

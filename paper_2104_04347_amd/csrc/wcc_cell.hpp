@@ -18,6 +18,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "wcc_rn.hpp"
+
 namespace wcc {
 
 constexpr int kAdvection = 0, kBurgers = 1, kEuler = 2;
@@ -67,17 +69,17 @@ __device__ __forceinline__ double fmaT(double a, double b, double c) { return __
 __device__ __forceinline__ float fmaT(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 __device__ __forceinline__ double absT(double a) { return __builtin_fabs(a); }
 __device__ __forceinline__ float absT(float a) { return __builtin_fabsf(a); }
-__device__ __forceinline__ double sqrtT(double a) { return __builtin_sqrt(a); }
+__device__ __forceinline__ double sqrtT(double a) { return sqrt_rn(a); }
 __device__ __forceinline__ float sqrtT(float a) { return __builtin_amdgcn_sqrtf(a); }
 __device__ __forceinline__ bool finiteT(double a) { return __builtin_isfinite(a); }
 
-// Division in the bulk type.  binary64: the IEEE quotient (the binary64 mode
-// is bit-reproducible).  binary32 (FP32-mixed mode, checked against the FP64
+// Division in the bulk type.  binary64: the correctly rounded quotient
+// (div_rn; the binary64 mode is bit-reproducible).  binary32 (FP32-mixed mode, checked against the FP64
 // oracle with a tolerance): the hardware reciprocal (1 ulp) times the
 // numerator, both scaled by 2^100 when the divisor is below 2^-100 so that
 // subnormal divisors (the limiter's epsilon is a binary32 subnormal) do not
 // overflow the reciprocal; the scaling by a power of two is exact.
-__device__ __forceinline__ double divT(double a, double b) { return a / b; }
+__device__ __forceinline__ double divT(double a, double b) { return div_rn(a, b); }
 __device__ __forceinline__ float divT(float a, float b) {
   const bool tiny = __builtin_fabsf(b) < 0x1p-100f;
   const float s = tiny ? 0x1p100f : 1.0f;
@@ -263,19 +265,19 @@ __device__ __forceinline__ void limiter_weights(double b0, double b1, double b2,
                                                 double& w0, double& w1, double& w2) {
   double wh0, wh1, wh2;
   if (P == 1) {
-    const double q0 = 1.0 / (b0 + eps), q1 = 1.0 / (b1 + eps), q2 = 1.0 / (b2 + eps);
+    const double q0 = div_rn(1.0, b0 + eps), q1 = div_rn(1.0, b1 + eps), q2 = div_rn(1.0, b2 + eps);
     wh0 = q0 * q0;
     wh1 = q1 * q1;
     wh2 = q2 * q2;
   } else {
-    const double r0 = st / __builtin_fma(b0, b0, eps);
-    const double r1 = st / __builtin_fma(b1, b1, eps);
-    const double r2 = st / __builtin_fma(b2, b2, eps);
+    const double r0 = div_rn(st, __builtin_fma(b0, b0, eps));
+    const double r1 = div_rn(st, __builtin_fma(b1, b1, eps));
+    const double r2 = div_rn(st, __builtin_fma(b2, b2, eps));
     wh0 = __builtin_fma(r0, r0, 1.0);
     wh1 = r1 * r1;
     wh2 = r2 * r2;
   }
-  const double inv = 1.0 / ((wh0 + wh1) + wh2);
+  const double inv = div_rn(1.0, (wh0 + wh1) + wh2);
   w0 = wh0 * inv;
   w1 = wh1 * inv;
   w2 = wh2 * inv;

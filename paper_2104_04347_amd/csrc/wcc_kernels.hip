@@ -52,7 +52,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(min_waves_p
 void k_half_step(const StepArgs<R> a) {
   double dt;
   if (!step_time(a.ctrl, a.parts, a.slot, a.dx, a.dt_fixed, blockIdx.x == 0 && threadIdx.x < 64, dt)) return;
-  const double lam = dt / a.dx;
+  const double lam = div_rn(dt, a.dx);
   const R nlam = (R)(-lam);
   // the wave index is the same in every lane: say so, so that tile and
   // instance indices live in scalar registers

@@ -161,7 +161,7 @@ template <int EQ, int P, bool LIM, class R>
 __global__ __launch_bounds__(256) void k_half_step_wide(const StepArgs<R> a) {
   double dt;
   if (!step_time(a.ctrl, a.parts, a.slot, a.dx, a.dt_fixed, blockIdx.x == 0 && threadIdx.x < 64, dt)) return;
-  const double lam = dt / a.dx;
+  const double lam = div_rn(dt, a.dx);
   const R nlam = (R)(-lam);
   const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6),
             nw = blockDim.x >> 6;

@@ -62,7 +62,7 @@ __device__ __forceinline__ bool step_time(Ctrl* ctrl, unsigned long long* parts,
                               : __longlong_as_double((long long)ctrl->smax[slot]);
     const double tend = ctrl->t_end;
     done = done || !(t < tend);
-    dt = (ctrl->cfl * dx) / smax;
+    dt = div_rn(ctrl->cfl * dx, smax);
     const double rem = tend - t;
     if (dt >= rem) {
       dt = rem;

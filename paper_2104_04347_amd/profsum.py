@@ -6,7 +6,7 @@ Measurement tooling; runs on any host, no GPU needed.
       per-kernel dispatch table (calls, total / mean / min / max duration,
       register counts, grid and workgroup sizes) from a --kernel-trace run
 
-  python -m paper_2104_04347_amd.profsum trace DB --last K
+  python -m paper_2104_04347_amd.profsum trace DB --last K [--skip S]
       the same over each kernel's last K dispatches in launch order (the
       timed half-steps of a run, without its warm-up dispatches)
 
@@ -48,10 +48,12 @@ COPY_KERNEL = "__amd_rocclr_copyBuffer"
 
 # the sources the single-instance 1D half-step kernel is compiled from, and
 # those of the 2D half-step kernels
-KERNEL_SOURCES = ("wcc_cell.hpp", "wcc_internal.hpp", "wcc_kernels.hip", "wcc_tile.hpp")
-KERNEL_SOURCES_2D = ("wcc2d_cell.hpp", "wcc2d_internal.hpp", "wcc2d_kernels.hip", "wcc_internal.hpp", "wcc_tile.hpp")
+KERNEL_SOURCES = ("wcc_cell.hpp", "wcc_internal.hpp", "wcc_kernels.hip", "wcc_tile.hpp", "wcc_rn.hpp")
+KERNEL_SOURCES_2D = ("wcc2d_cell.hpp", "wcc2d_internal.hpp", "wcc2d_kernels.hip", "wcc_internal.hpp", "wcc_tile.hpp",
+                     "wcc_rn.hpp")
 # the 1D kernel with two old cells per lane (launch variant 4)
-KERNEL_SOURCES_WIDE = ("wcc_cell.hpp", "wcc_internal.hpp", "wcc_kernels_wide.hip", "wcc_tile.hpp", "wcc_wide.hpp")
+KERNEL_SOURCES_WIDE = ("wcc_cell.hpp", "wcc_internal.hpp", "wcc_kernels_wide.hip", "wcc_tile.hpp", "wcc_wide.hpp",
+                       "wcc_rn.hpp")
 SOURCE_SETS = {"1d": KERNEL_SOURCES, "2d": KERNEL_SOURCES_2D, "1d_wide": KERNEL_SOURCES_WIDE}
 
 
@@ -78,12 +80,14 @@ def kernel_source_hash(sources: str = "1d", read=None) -> str:
     return h.hexdigest()
 
 
-def trace_table(db: str, last: int = 0) -> str:
+def trace_table(db: str, last: int = 0, skip: int = 0) -> str:
     con = sqlite3.connect(db)
     if last > 0:
-        # each kernel's last `last` dispatches (launch order = start time)
+        # each kernel's last `last` dispatches (launch order = start time),
+        # before its last `skip` ones
         con.execute(f"""create temp view sel as select * from (select *, row_number() over
-                        (partition by name order by start desc) as rn from kernels) where rn <= {int(last)}""")
+                        (partition by name order by start desc) as rn from kernels)
+                        where rn > {int(skip)} and rn <= {int(skip) + int(last)}""")
         table = "sel"
     else:
         table = "kernels"
@@ -201,6 +205,7 @@ def main(argv=None) -> None:
     t = sub.add_parser("trace")
     t.add_argument("db")
     t.add_argument("--last", type=int, default=0, help="only each kernel's last K dispatches")
+    t.add_argument("--skip", type=int, default=0, help="with --last: the K dispatches before each kernel's last S")
     i = sub.add_parser("insts")
     i.add_argument("db")
     i.add_argument("--kernel", required=True)
@@ -224,7 +229,7 @@ def main(argv=None) -> None:
     r.add_argument("--out")
     a = ap.parse_args(argv)
     if a.cmd == "trace":
-        print(trace_table(a.db, a.last))
+        print(trace_table(a.db, a.last, a.skip))
     elif a.cmd == "counters":
         print(counters_table(a.db))
     elif a.cmd == "insts":
