@@ -29,7 +29,12 @@ WINDOW = 30     # instructions after the fixup in which the remainder must appea
 def _disassemble(lib: str, tmp) -> list:
     """Disassembly (lines) of every gfx950 code object in lib's offload bundles."""
     fat = tmp / "fatbin"
-    subprocess.run(["objcopy", "--dump-section", f".hip_fatbin={fat}", lib], check=True, capture_output=True)
+    # objcopy rewrites its input file when given no output file, so it works
+    # on a private copy: the library itself is mapped into this process
+    copy = tmp / "lib.so"
+    shutil.copyfile(lib, copy)
+    subprocess.run(["objcopy", "--dump-section", f".hip_fatbin={fat}", str(copy), str(tmp / "discard.so")],
+                   check=True, capture_output=True)
     data = fat.read_bytes()
     starts = [m.start() for m in re.finditer(re.escape(MAGIC), data)]
     assert starts, "no offload bundle in the library"
